@@ -1,0 +1,172 @@
+/*
+ * fe.h - C ABI of an FFT-based elasticity homogenization solver for AMD
+ * MI355X (gfx950).
+ *
+ * The solver runs the Lippmann-Schwinger fixed-point iteration of
+ * F. Willot, "Fourier-based schemes for computing the mechanical response
+ * of composites with accurate local fields" (arXiv 1412.8398), on a
+ * periodic voxel grid:
+ *
+ *   tau = (C - C0) : eps                       polarization, eq. (6)
+ *   e   = eps_bar - G' * tau                   Green operator, eqs. (6), (24)
+ *   DS: eps <- e                               direct scheme, eq. (9)
+ *   AS: eps <- eps + 2 (C + C0)^-1 C0 : (e - eps)   accelerated scheme, eq. (16)
+ *
+ * until the equilibrium norm eta of eq. (43) falls below a tolerance.  G' is
+ * one of the continuous Moulinec-Suquet operator (eq. (8) with the Nyquist
+ * rule of eq. (14)), the Willot-Pellegrini operator (k of eq. (21)), or the
+ * rotated-grid operator (k of eq. (36), zeroed where eq. (41) says).
+ *
+ * Conventions shared by every entry point
+ *   - grid: nx, ny, nz voxels; device fields are C-ordered [z][y][x], x fastest.
+ *   - tensor fields are structure-of-arrays with 6 planes of N = nx*ny*nz
+ *     values in tensor Voigt order (11, 22, 33, 23, 13, 12); shear planes
+ *     hold the tensor component eps_ij, not the engineering strain 2 eps_ij.
+ *   - macroscopic strains are 6 doubles in the same order.
+ *   - phase maps are uint8, one label per voxel, labels < n_phases.
+ *   - every device pointer is caller-owned memory on the device the plan was
+ *     created on; the library keeps no pointer after a call returns.
+ *   - functions return a status; negative values are errors for which nothing
+ *     was written to the outputs; fe_last_error() gives a thread-local message.
+ *   - argument checks happen before any device work.
+ */
+#ifndef FE_H_
+#define FE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FE_OK = 0,               /* converged: eta <= tol                           */
+  FE_NOT_CONVERGED = 1,    /* iteration cap reached; outputs hold the last iterate */
+  FE_DIVERGED = 2,         /* eta non-finite or growing; outputs hold the last iterate */
+  FE_ERR_INVALID_ARG = -1, /* a bad argument; nothing was run                 */
+  FE_ERR_UNSUPPORTED = -2, /* valid but not supported (e.g. a grid size)      */
+  FE_ERR_OOM = -3,         /* device allocation failed                        */
+  FE_ERR_DEVICE = -4       /* a HIP runtime error                             */
+} fe_status;
+
+/* Discrete Green operator (§3, §4 of the paper). */
+typedef enum {
+  FE_GREEN_MS = 0,  /* continuous operator, k = i q, eqs. (8), (14)       */
+  FE_GREEN_WP = 1,  /* Willot-Pellegrini, k = exp(i q) - 1, eq. (21)       */
+  FE_GREEN_ROT = 2  /* rotated grid, k of eq. (36), special modes eq. (41)  */
+} fe_discretization;
+
+typedef enum { FE_DIRECT = 0, FE_ACCELERATED = 1 } fe_scheme; /* eqs. (9), (16) */
+
+/* Arithmetic of the fields, FFTs and Green operator.  Reductions (eta, mean
+ * stress), reference-medium constants and the verification residual are
+ * always float64. */
+typedef enum { FE_FP64 = 0, FE_FP32 = 1 } fe_precision;
+
+/* Reference medium C0 (isotropic). */
+typedef enum {
+  FE_REF_PAPER = 0,    /* AS: kappa0 = sqrt(kmin kmax), mu0 = sqrt(mumin mumax), eq. (17);
+                          DS: kappa0 = beta (kmin + kmax), mu0 = beta (mumin + mumax), eq. (18) */
+  FE_REF_EXPLICIT = 1  /* Young's modulus E0 and Poisson ratio nu0 given (§6.1) */
+} fe_ref_rule;
+
+typedef struct {
+  int32_t nx, ny, nz;
+} fe_grid;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(fe_plan_options)                             */
+  fe_precision precision; /* default FE_FP32                                      */
+  int32_t max_iter;       /* iteration cap, default 1000                          */
+  int32_t ref_rule;       /* fe_ref_rule, default FE_REF_PAPER                     */
+  double ds_beta;         /* beta of eq. (18), default 0.5                         */
+  double E0, nu0;         /* used when ref_rule == FE_REF_EXPLICIT                 */
+  int32_t check_every;    /* evaluate eta every m iterations (default 1); the
+                             iteration count is then a multiple of m            */
+  int32_t diverge_window; /* report FE_DIVERGED after this many consecutive
+                             increases of eta (default 50; 0 disables)          */
+  void* hip_stream;       /* hipStream_t to run on; NULL = the null stream        */
+} fe_plan_options;
+
+typedef struct fe_plan fe_plan;
+
+/* Fill *opt with the defaults above. */
+void fe_plan_options_default(fe_plan_options* opt);
+
+/*
+ * Create a plan: validates the grid (each of nx, ny, nz even, of the form
+ * 2^a 3^b, between 4 and 1024), allocates the device workspace and builds
+ * the FP64 twiddle and wave-vector tables.  opt may be NULL (defaults).
+ * Errors: FE_ERR_INVALID_ARG (bad enum/size), FE_ERR_UNSUPPORTED (size outside
+ * the supported set), FE_ERR_OOM, FE_ERR_DEVICE.
+ */
+fe_status fe_plan_create(fe_grid grid, fe_discretization disc, fe_scheme scheme,
+                         const fe_plan_options* opt, fe_plan** out);
+
+/* Release a plan and its workspace (NULL is ignored). */
+void fe_plan_destroy(fe_plan* plan);
+
+/* Device bytes held by the plan's workspace. */
+size_t fe_plan_workspace_bytes(const fe_plan* plan);
+
+/* Per-phase isotropic moduli, host memory, float64: E > 0, -1 < nu < 0.5. */
+typedef struct {
+  int32_t n_phases; /* 1..256 */
+  const double* E;
+  const double* nu;
+} fe_materials;
+
+typedef struct {
+  /* inputs (may be NULL) */
+  void* strain;            /* device, 6*N of the plan precision: receives eps^n       */
+  void* stress;            /* device, 6*N of the plan precision: receives C:eps^n     */
+  double* eta_history;     /* host, receives eta^k for k = 0..min(n, capacity-1)      */
+  int32_t history_capacity;
+  /* outputs */
+  double mean_stress[6];   /* <sigma^n>, float64 volume average (eq. (5))             */
+  double eta;              /* eta^n, eq. (43), float64 reduction                      */
+  double eta_verify_fp64;  /* eta^n recomputed with float64 arithmetic from eps^n
+                              (equals eta for FE_FP64 plans)                           */
+  int32_t iterations;      /* n: first k with eta^k <= tol, or the cap                */
+  double seconds;          /* wall time of the iteration loop on the device stream    */
+} fe_result;
+
+/*
+ * Solve one load case.
+ *   phase        device, N uint8 labels (checked on the device; a label
+ *                >= n_phases gives FE_ERR_INVALID_ARG after the check kernel)
+ *   materials    host table of per-phase (E, nu)
+ *   macro_strain host, 6 doubles, tensor Voigt order (eq. (4): <eps> = eps_bar)
+ *   tol          > 0; iteration stops at the first k with eta^k <= tol
+ *   strain_init  device, 6*N of the plan precision, or NULL for eps^0 = eps_bar
+ *                (eq. (9)); its mean need not equal eps_bar
+ *   out          result; out->strain may be NULL (the plan then keeps the
+ *                iterate in its own workspace)
+ * Returns FE_OK, FE_NOT_CONVERGED or FE_DIVERGED with out filled, or an error.
+ */
+fe_status fe_solve(fe_plan* plan, const uint8_t* phase, fe_materials materials,
+                   const double macro_strain[6], double tol, const void* strain_init,
+                   fe_result* out);
+
+/*
+ * Effective stiffness (eq. (5)) from the six unit macroscopic strains:
+ * C_voigt[6*I + J] is <sigma_I> for a normal load J (eps_bar_JJ = 1) and
+ * <sigma_I>/2 for a shear load J (eps_bar_ab = eps_bar_ba = 1).
+ * iterations[J] receives the iteration count of load J (may be NULL).
+ * Returns the worst status over the six solves.
+ */
+fe_status fe_effective_stiffness(fe_plan* plan, const uint8_t* phase, fe_materials materials,
+                                 double tol, double C_voigt[36], int32_t iterations[6]);
+
+/* Human-readable name of a status code (static string). */
+const char* fe_status_string(fe_status s);
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char* fe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_H_ */

@@ -233,9 +233,11 @@ def _wave_vector_from_modes(op, ms, Ls):
             _, s = _cos_sin(ms[a], Ls[a])
             k[a] = 1j * s
     elif op == "W":
+        # exp(i q) - 1 written as -2 sin^2(q/2) + 2 i sin(q/2) cos(q/2), which
+        # is the same number without the cancellation of cos(q) - 1 at small q
         for a in range(3):
-            c, s = _cos_sin(ms[a], Ls[a])
-            k[a] = (c - 1.0) + 1j * s
+            ch, sh = _cos_sin(ms[a], 2 * Ls[a])
+            k[a] = -2.0 * sh * sh + 2j * sh * ch
     elif op == "R":
         # half angles q_a/2 = 2 pi m_a / (2 L_a)
         ch, sh = zip(*(_cos_sin(ms[a], 2 * Ls[a]) for a in range(3)))

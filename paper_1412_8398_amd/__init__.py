@@ -1,0 +1,247 @@
+"""Python binding of ``libfe.so``: argument marshalling only.
+
+Every step of the solve runs in the library's HIP kernels; PyTorch tensors
+serve as device memory.  The binding raises if the library is not built --
+there is no CPU fallback.
+
+The C ABI is declared in ``include/fe.h``; names mirror it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "FE_OK", "FE_NOT_CONVERGED", "FE_DIVERGED", "FE_ERR_INVALID_ARG", "FE_ERR_UNSUPPORTED",
+    "FE_ERR_OOM", "FE_ERR_DEVICE", "GREEN", "SCHEME", "PRECISION", "FeError", "Plan", "Result",
+    "load_library", "library_path", "status_string", "last_error",
+]
+
+FE_OK, FE_NOT_CONVERGED, FE_DIVERGED = 0, 1, 2
+FE_ERR_INVALID_ARG, FE_ERR_UNSUPPORTED, FE_ERR_OOM, FE_ERR_DEVICE = -1, -2, -3, -4
+
+GREEN = {"MS": 0, "WP": 1, "W": 1, "ROT": 2, "R": 2}
+SCHEME = {"DS": 0, "direct": 0, "AS": 1, "accelerated": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+REF_RULE = {"paper": 0, "explicit": 1}
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.environ.get("FE_LIBRARY", os.path.join(_PKG, "libfe.so"))
+
+
+class FeGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32)]
+
+
+class FePlanOptions(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("precision", C.c_int),
+        ("max_iter", C.c_int32),
+        ("ref_rule", C.c_int32),
+        ("ds_beta", C.c_double),
+        ("E0", C.c_double),
+        ("nu0", C.c_double),
+        ("check_every", C.c_int32),
+        ("diverge_window", C.c_int32),
+        ("hip_stream", C.c_void_p),
+    ]
+
+
+class FeMaterials(C.Structure):
+    _fields_ = [("n_phases", C.c_int32), ("E", C.POINTER(C.c_double)), ("nu", C.POINTER(C.c_double))]
+
+
+class FeResult(C.Structure):
+    _fields_ = [
+        ("strain", C.c_void_p),
+        ("stress", C.c_void_p),
+        ("eta_history", C.POINTER(C.c_double)),
+        ("history_capacity", C.c_int32),
+        ("mean_stress", C.c_double * 6),
+        ("eta", C.c_double),
+        ("eta_verify_fp64", C.c_double),
+        ("iterations", C.c_int32),
+        ("seconds", C.c_double),
+    ]
+
+
+_LIB = None
+
+
+def load_library():
+    """Load libfe.so; raise if it has not been built (no fallback path)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: build it with "
+                           "`python -m paper_1412_8398_amd.build`")
+    lib = C.CDLL(path)
+    lib.fe_plan_options_default.argtypes = [C.POINTER(FePlanOptions)]
+    lib.fe_plan_options_default.restype = None
+    lib.fe_plan_create.argtypes = [FeGrid, C.c_int, C.c_int, C.POINTER(FePlanOptions), C.POINTER(C.c_void_p)]
+    lib.fe_plan_create.restype = C.c_int
+    lib.fe_plan_destroy.argtypes = [C.c_void_p]
+    lib.fe_plan_destroy.restype = None
+    lib.fe_plan_workspace_bytes.argtypes = [C.c_void_p]
+    lib.fe_plan_workspace_bytes.restype = C.c_size_t
+    lib.fe_solve.argtypes = [C.c_void_p, C.c_void_p, FeMaterials, C.POINTER(C.c_double), C.c_double, C.c_void_p,
+                             C.POINTER(FeResult)]
+    lib.fe_solve.restype = C.c_int
+    lib.fe_effective_stiffness.argtypes = [C.c_void_p, C.c_void_p, FeMaterials, C.c_double,
+                                           C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+    lib.fe_effective_stiffness.restype = C.c_int
+    lib.fe_status_string.argtypes = [C.c_int]
+    lib.fe_status_string.restype = C.c_char_p
+    lib.fe_last_error.argtypes = []
+    lib.fe_last_error.restype = C.c_char_p
+    _LIB = lib
+    return lib
+
+
+def status_string(s: int) -> str:
+    return load_library().fe_status_string(s).decode()
+
+
+def last_error() -> str:
+    return load_library().fe_last_error().decode()
+
+
+class FeError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)}: {last_error()}")
+
+
+def _ptr(x) -> int | None:
+    """Device address of a torch tensor (or an int address); None for None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if not x.is_cuda:
+        raise ValueError("expected a device (cuda) tensor")
+    if not x.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return x.data_ptr()
+
+
+def _materials(E, nu):
+    E = np.ascontiguousarray(np.atleast_1d(np.asarray(E, dtype=np.float64)))
+    nu = np.ascontiguousarray(np.atleast_1d(np.asarray(nu, dtype=np.float64)))
+    if E.shape != nu.shape:
+        raise ValueError("E and nu must have the same length")
+    m = FeMaterials(int(E.size), E.ctypes.data_as(C.POINTER(C.c_double)), nu.ctypes.data_as(C.POINTER(C.c_double)))
+    return m, (E, nu)  # keep the arrays alive
+
+
+@dataclass
+class Result:
+    status: int
+    iterations: int
+    eta: float
+    eta_verify_fp64: float
+    mean_stress: np.ndarray
+    seconds: float
+    eta_history: np.ndarray = field(default=None, repr=False)
+
+    @property
+    def converged(self) -> bool:
+        return self.status == FE_OK
+
+
+class Plan:
+    """A solver plan for one grid, Green operator and scheme (fe_plan_create)."""
+
+    def __init__(self, grid, green="R", scheme="AS", precision="fp32", max_iter=1000, ref_rule="paper",
+                 ds_beta=0.5, E0=0.0, nu0=0.25, check_every=1, diverge_window=50, stream=None):
+        lib = load_library()
+        nx, ny, nz = (grid, grid, grid) if isinstance(grid, int) else tuple(grid)
+        self.shape = (nz, ny, nx)
+        self.precision = precision
+        opt = FePlanOptions()
+        lib.fe_plan_options_default(C.byref(opt))
+        opt.precision = PRECISION[precision]
+        opt.max_iter = int(max_iter)
+        opt.ref_rule = REF_RULE[ref_rule]
+        opt.ds_beta = float(ds_beta)
+        opt.E0 = float(E0)
+        opt.nu0 = float(nu0)
+        opt.check_every = int(check_every)
+        opt.diverge_window = int(diverge_window)
+        opt.hip_stream = stream
+        h = C.c_void_p()
+        s = lib.fe_plan_create(FeGrid(nx, ny, nz), GREEN[green], SCHEME[scheme], C.byref(opt), C.byref(h))
+        if s != FE_OK:
+            raise FeError(s, "fe_plan_create")
+        self._h = h
+        self._lib = lib
+
+    @property
+    def n(self) -> int:
+        nz, ny, nx = self.shape
+        return nx * ny * nz
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self._lib.fe_plan_workspace_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fe_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def solve(self, phase, E, nu, macro_strain, tol, strain_init=None, strain=None, stress=None, history=0,
+              raise_on_error=True) -> Result:
+        """fe_solve.  ``phase`` is a device uint8 tensor of the grid's shape;
+        ``strain``/``stress`` optional device tensors (6, nz, ny, nx) of the
+        plan precision that receive eps^n and sigma^n."""
+        m, keep = _materials(E, nu)
+        macro = (C.c_double * 6)(*[float(v) for v in macro_strain])
+        r = FeResult()
+        r.strain = _ptr(strain)
+        r.stress = _ptr(stress)
+        hist = None
+        if history:
+            hist = np.zeros(int(history), dtype=np.float64)
+            r.eta_history = hist.ctypes.data_as(C.POINTER(C.c_double))
+            r.history_capacity = int(history)
+        s = self._lib.fe_solve(self._h, _ptr(phase), m, macro, float(tol), _ptr(strain_init), C.byref(r))
+        if s < 0 and raise_on_error:
+            raise FeError(s, "fe_solve")
+        del keep
+        res = Result(s, r.iterations, r.eta, r.eta_verify_fp64, np.array(r.mean_stress[:]), r.seconds)
+        if hist is not None:
+            res.eta_history = hist[: min(len(hist), r.iterations + 1)]
+        return res
+
+    def effective_stiffness(self, phase, E, nu, tol):
+        """fe_effective_stiffness: 6x6 Voigt matrix and the six iteration counts."""
+        m, keep = _materials(E, nu)
+        Cv = (C.c_double * 36)()
+        its = (C.c_int32 * 6)()
+        s = self._lib.fe_effective_stiffness(self._h, _ptr(phase), m, float(tol), Cv, its)
+        if s < 0:
+            raise FeError(s, "fe_effective_stiffness")
+        del keep
+        return np.array(Cv[:]).reshape(6, 6), list(its), s

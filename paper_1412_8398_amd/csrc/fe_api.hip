@@ -1,0 +1,659 @@
+// C ABI of the solver (include/fe.h): validation, plans, the iteration loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fe.h"
+#include "fe_kernels.h"
+
+using namespace fe;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static fe_status fail(fe_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? FE_ERR_OOM : FE_ERR_DEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                         \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// host-side tables (float64)
+// ---------------------------------------------------------------------------
+static bool is_2a3b(int n) {
+  if (n <= 0) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+// Radix sequence for the Stockham stages: radix 8 first, then 4, 2, 3.
+static uint32_t radix_plan(int n) {
+  uint32_t plan = 0;
+  int s = 0;
+  auto push = [&](int r) { plan |= (uint32_t)r << (4 * s++); };
+  while (n % 8 == 0) { push(8); n /= 8; }
+  while (n % 4 == 0) { push(4); n /= 4; }
+  while (n % 2 == 0) { push(2); n /= 2; }
+  while (n % 3 == 0) { push(3); n /= 3; }
+  return s <= 8 ? plan : 0;
+}
+
+// cos and sin of 2 pi num / den, exact at multiples of pi/2.  The angle is
+// first reduced to (-pi, pi] so that small angles keep full relative accuracy
+// (sin of an argument near 2 pi loses it).
+static void cos_sin(long num, long den, double* c, double* s) {
+  long r = ((num % den) + den) % den;  // [0, den)
+  if ((4 * r) % den == 0) {
+    static const double cc[4] = {1, 0, -1, 0}, ss[4] = {0, 1, 0, -1};
+    int k = (int)((4 * r) / den);
+    *c = cc[k];
+    *s = ss[k];
+    return;
+  }
+  if (2 * r > den) r -= den;  // (-den/2, den/2]
+  const double a = 2.0 * M_PI * (double)r / (double)den;
+  *c = std::cos(a);
+  *s = std::sin(a);
+}
+
+// m' of eq. (12): m if 2m <= n else m - n (Nyquist at +n/2 for even n).
+static long signed_mode(long m, long n) { return 2 * m <= n ? m : m - n; }
+
+static std::vector<double> twiddles(int n) {  // exp(-2 pi i k / n), interleaved
+  std::vector<double> t(2 * n);
+  for (int k = 0; k < n; ++k) {
+    double c, s;
+    cos_sin(k, n, &c, &s);
+    t[2 * k] = c;
+    t[2 * k + 1] = -s;
+  }
+  return t;
+}
+
+static std::vector<double> wave_table(int n, int op) {
+  std::vector<double> w(2 * n);
+  for (int m = 0; m < n; ++m) {
+    const long mp = signed_mode(m, n);
+    if (op == OP_ROT) {  // half angle q/2 = 2 pi mp / (2n)
+      double c, s;
+      cos_sin(mp, 2L * n, &c, &s);
+      w[2 * m] = s;
+      w[2 * m + 1] = c;
+    } else if (op == OP_WP) {
+      // exp(i q) - 1 = -2 sin^2(q/2) + i 2 sin(q/2) cos(q/2): no cancellation at small q
+      double ch, sh;
+      cos_sin(mp, 2L * n, &ch, &sh);
+      w[2 * m] = -2.0 * sh * sh;
+      w[2 * m + 1] = 2.0 * sh * ch;
+    } else {  // MS
+      w[2 * m] = 2.0 * M_PI * (double)mp / (double)n;
+      w[2 * m + 1] = (n % 2 == 0 && 2 * m == n) ? 1.0 : 0.0;
+    }
+  }
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Tables {
+  cpx<T>* tw[3] = {nullptr, nullptr, nullptr};
+  T* wave[3] = {nullptr, nullptr, nullptr};
+};
+
+struct fe_plan {
+  fe_grid grid;
+  fe_discretization disc;
+  fe_scheme scheme;
+  fe_plan_options opt;
+  int device;
+  hipStream_t stream;
+  int op;
+  bool displacement;  // WP/ROT: 3-component displacement form
+  Dims d;
+  uint32_t plan_x, plan_y, plan_z;
+  int div_blocks;
+  size_t partial_count;
+  // workspace
+  void* eps_ws = nullptr;
+  void* R = nullptr;
+  void* S = nullptr;
+  double* partials = nullptr;
+  double* partials2 = nullptr;
+  double* red = nullptr;
+  double* h_red = nullptr;  // pinned
+  int* flag = nullptr;
+  void* coef = nullptr;
+  PhaseCoef<double>* coef64 = nullptr;
+  Tables<float> t32;
+  Tables<double> t64;
+  size_t ws_bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+static size_t elem_size(const fe_plan* p) { return p->opt.precision == FE_FP64 ? 8 : 4; }
+
+extern "C" void fe_plan_options_default(fe_plan_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->struct_size = sizeof(fe_plan_options);
+  o->precision = FE_FP32;
+  o->max_iter = 1000;
+  o->ref_rule = FE_REF_PAPER;
+  o->ds_beta = 0.5;
+  o->E0 = 0.0;
+  o->nu0 = 0.25;
+  o->check_every = 1;
+  o->diverge_window = 50;
+  o->hip_stream = nullptr;
+}
+
+static hipError_t dmalloc(fe_plan* p, void** ptr, size_t bytes) {
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e == hipSuccess) p->ws_bytes += bytes;
+  return e;
+}
+
+template <typename T>
+static fe_status upload_tables(fe_plan* p, Tables<T>& t) {
+  const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
+  for (int a = 0; a < 3; ++a) {
+    std::vector<double> tw = twiddles(n[a]);
+    std::vector<double> wv = wave_table(n[a], p->op);
+    std::vector<T> tw_t(tw.begin(), tw.end()), wv_t(wv.begin(), wv.end());
+    HIP_TRY(dmalloc(p, (void**)&t.tw[a], tw_t.size() * sizeof(T)));
+    HIP_TRY(dmalloc(p, (void**)&t.wave[a], wv_t.size() * sizeof(T)));
+    HIP_TRY(hipMemcpy(t.tw[a], tw_t.data(), tw_t.size() * sizeof(T), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t.wave[a], wv_t.data(), wv_t.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+  return FE_OK;
+}
+
+static std::once_flag g_attr_once[64];
+
+extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme scheme, const fe_plan_options* opt,
+                                    fe_plan** out) {
+  if (!out) return fail(FE_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  fe_plan_options o;
+  fe_plan_options_default(&o);
+  if (opt) {
+    if (opt->struct_size != sizeof(fe_plan_options))
+      return fail(FE_ERR_INVALID_ARG, "fe_plan_options.struct_size is %u, expected %zu", opt->struct_size,
+                  sizeof(fe_plan_options));
+    o = *opt;
+  }
+  if (disc < FE_GREEN_MS || disc > FE_GREEN_ROT) return fail(FE_ERR_INVALID_ARG, "unknown discretization %d", (int)disc);
+  if (scheme != FE_DIRECT && scheme != FE_ACCELERATED) return fail(FE_ERR_INVALID_ARG, "unknown scheme %d", (int)scheme);
+  if (o.precision != FE_FP32 && o.precision != FE_FP64)
+    return fail(FE_ERR_INVALID_ARG, "unknown precision %d", (int)o.precision);
+  if (o.max_iter < 0) return fail(FE_ERR_INVALID_ARG, "max_iter must be >= 0");
+  if (o.check_every < 1) return fail(FE_ERR_INVALID_ARG, "check_every must be >= 1");
+  if (o.diverge_window < 0) return fail(FE_ERR_INVALID_ARG, "diverge_window must be >= 0");
+  if (o.ref_rule != FE_REF_PAPER && o.ref_rule != FE_REF_EXPLICIT)
+    return fail(FE_ERR_INVALID_ARG, "unknown ref_rule %d", o.ref_rule);
+  if (o.ref_rule == FE_REF_PAPER && scheme == FE_DIRECT && !(o.ds_beta > 0.0 && std::isfinite(o.ds_beta)))
+    return fail(FE_ERR_INVALID_ARG, "ds_beta must be positive and finite");
+  if (o.ref_rule == FE_REF_EXPLICIT &&
+      !(std::isfinite(o.E0) && o.E0 > 0.0 && std::isfinite(o.nu0) && o.nu0 > -1.0 && o.nu0 < 0.5))
+    return fail(FE_ERR_INVALID_ARG, "explicit reference needs E0 > 0 and -1 < nu0 < 0.5");
+  const int n[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] <= 0) return fail(FE_ERR_INVALID_ARG, "grid dimension %d is %d", a, n[a]);
+    if (n[a] < 4 || n[a] > 1024 || n[a] % 2 != 0 || !is_2a3b(n[a]))
+      return fail(FE_ERR_UNSUPPORTED, "grid dimension %d = %d: need an even 2^a 3^b in [4, 1024]", a, n[a]);
+  }
+
+  fe_plan* p = new fe_plan();
+  p->grid = g;
+  p->disc = disc;
+  p->scheme = scheme;
+  p->opt = o;
+  p->stream = (hipStream_t)o.hip_stream;
+  p->op = disc == FE_GREEN_MS ? OP_MS : (disc == FE_GREEN_WP ? OP_WP : OP_ROT);
+  p->displacement = p->op != OP_MS;
+  p->d.nx = g.nx;
+  p->d.ny = g.ny;
+  p->d.nz = g.nz;
+  p->d.H = g.nz / 2 + 1;
+  p->d.N = (long long)g.nx * g.ny * g.nz;
+  p->plan_x = radix_plan(g.nx);
+  p->plan_y = radix_plan(g.ny);
+  p->plan_z = radix_plan(g.nz);
+  long long db = (p->d.N + kThreads - 1) / kThreads;
+  p->div_blocks = (int)(db > kMaxReduceBlocks ? kMaxReduceBlocks : db);
+
+  auto cleanup_fail = [&](fe_status s) {
+    std::string keep = g_last_error;
+    fe_plan_destroy(p);
+    g_last_error = keep;
+    return s;
+  };
+  if (hipGetDevice(&p->device) != hipSuccess) return cleanup_fail(fail(FE_ERR_DEVICE, "no HIP device"));
+  if (p->device < 64) {
+    int bad = 0;
+    std::call_once(g_attr_once[p->device], [&] {
+      bad |= Launch<float>::set_kernel_attributes();
+      bad |= Launch<double>::set_kernel_attributes();
+    });
+    if (bad) return cleanup_fail(fail(FE_ERR_DEVICE, "hipFuncSetAttribute failed"));
+  }
+  const size_t es = elem_size(p);
+  const int ncomp = p->displacement ? 3 : 6;
+  const long long N = p->d.N;
+  const size_t spec = (size_t)p->d.H * g.ny * g.nx;
+  fe_status st;
+  hipError_t e;
+  if ((e = dmalloc(p, &p->R, (size_t)ncomp * N * es)) != hipSuccess)
+    return cleanup_fail(fail(e == hipErrorOutOfMemory ? FE_ERR_OOM : FE_ERR_DEVICE, "workspace R: %s", hipGetErrorString(e)));
+  if ((e = dmalloc(p, &p->S, (size_t)ncomp * spec * 2 * es)) != hipSuccess)
+    return cleanup_fail(fail(e == hipErrorOutOfMemory ? FE_ERR_OOM : FE_ERR_DEVICE, "workspace S: %s", hipGetErrorString(e)));
+  // partial sums: div/tau blocks x 7, and one per x-line block of the spectral eta
+  const size_t lines = (size_t)p->d.H * g.ny;
+  p->partial_count = (size_t)kMaxReduceBlocks * 7;
+  if ((e = dmalloc(p, (void**)&p->partials, p->partial_count * sizeof(double))) != hipSuccess ||
+      (e = dmalloc(p, (void**)&p->partials2, (lines + 1) * sizeof(double))) != hipSuccess ||
+      (e = dmalloc(p, (void**)&p->red, 16 * sizeof(double))) != hipSuccess ||
+      (e = dmalloc(p, (void**)&p->flag, sizeof(int))) != hipSuccess ||
+      (e = dmalloc(p, &p->coef, 256 * sizeof(PhaseCoef<double>))) != hipSuccess ||
+      (e = dmalloc(p, (void**)&p->coef64, 256 * sizeof(PhaseCoef<double>))) != hipSuccess)
+    return cleanup_fail(fail(e == hipErrorOutOfMemory ? FE_ERR_OOM : FE_ERR_DEVICE, "workspace: %s", hipGetErrorString(e)));
+  if (hipHostMalloc((void**)&p->h_red, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return cleanup_fail(fail(FE_ERR_DEVICE, "pinned host buffer"));
+  if ((st = upload_tables<float>(p, p->t32)) != FE_OK) return cleanup_fail(st);
+  if ((st = upload_tables<double>(p, p->t64)) != FE_OK) return cleanup_fail(st);
+  if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
+    return cleanup_fail(fail(FE_ERR_DEVICE, "event creation"));
+  *out = p;
+  return FE_OK;
+}
+
+template <typename T>
+static void free_tables(Tables<T>& t) {
+  for (int a = 0; a < 3; ++a) {
+    if (t.tw[a]) (void)hipFree(t.tw[a]);
+    if (t.wave[a]) (void)hipFree(t.wave[a]);
+  }
+}
+
+extern "C" void fe_plan_destroy(fe_plan* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  void* bufs[] = {p->eps_ws, p->R, p->S, p->partials, p->partials2, p->red, p->flag, p->coef, p->coef64};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  free_tables(p->t32);
+  free_tables(p->t64);
+  if (p->h_red) (void)hipHostFree(p->h_red);
+  if (p->ev0) (void)hipEventDestroy(p->ev0);
+  if (p->ev1) (void)hipEventDestroy(p->ev1);
+  delete p;
+}
+
+extern "C" size_t fe_plan_workspace_bytes(const fe_plan* p) { return p ? p->ws_bytes : 0; }
+
+// ---------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------
+struct RefMedium {
+  double lam0, mu0, kap0;
+};
+
+static RefMedium reference_medium(const fe_plan* p, const fe_materials& m) {
+  RefMedium r;
+  if (p->opt.ref_rule == FE_REF_EXPLICIT) {
+    const double E = p->opt.E0, nu = p->opt.nu0;
+    r.lam0 = E * nu / ((1 + nu) * (1 - 2 * nu));
+    r.mu0 = E / (2 * (1 + nu));
+  } else {
+    double kmin = INFINITY, kmax = -INFINITY, mmin = INFINITY, mmax = -INFINITY;
+    for (int i = 0; i < m.n_phases; ++i) {
+      const double E = m.E[i], nu = m.nu[i];
+      const double lam = E * nu / ((1 + nu) * (1 - 2 * nu)), mu = E / (2 * (1 + nu));
+      const double kap = lam + 2.0 * mu / 3.0;
+      kmin = std::fmin(kmin, kap);
+      kmax = std::fmax(kmax, kap);
+      mmin = std::fmin(mmin, mu);
+      mmax = std::fmax(mmax, mu);
+    }
+    double k0, m0;
+    if (p->scheme == FE_ACCELERATED) {  // eq. (17)
+      k0 = std::sqrt(kmin * kmax);
+      m0 = std::sqrt(mmin * mmax);
+    } else {  // eq. (18)
+      k0 = p->opt.ds_beta * (kmin + kmax);
+      m0 = p->opt.ds_beta * (mmin + mmax);
+    }
+    r.mu0 = m0;
+    r.lam0 = k0 - 2.0 * m0 / 3.0;
+  }
+  r.kap0 = r.lam0 + 2.0 * r.mu0 / 3.0;
+  return r;
+}
+
+static std::vector<PhaseCoef<double>> phase_coefs(const fe_materials& m, const RefMedium& r) {
+  std::vector<PhaseCoef<double>> c(m.n_phases);
+  for (int i = 0; i < m.n_phases; ++i) {
+    const double E = m.E[i], nu = m.nu[i];
+    const double lam = E * nu / ((1 + nu) * (1 - 2 * nu)), mu = E / (2 * (1 + nu));
+    const double kap = lam + 2.0 * mu / 3.0;
+    c[i].lam = lam;
+    c[i].mu = mu;
+    c[i].dlam = lam - r.lam0;
+    c[i].dmu = mu - r.mu0;
+    c[i].ak = 2.0 * r.kap0 / (kap + r.kap0);
+    c[i].am = 2.0 * r.mu0 / (mu + r.mu0);
+    c[i].pad0 = c[i].pad1 = 0.0;
+  }
+  return c;
+}
+
+static fe_status validate_materials(const fe_materials& m) {
+  if (m.n_phases < 1 || m.n_phases > 256) return fail(FE_ERR_INVALID_ARG, "n_phases must be in [1, 256]");
+  if (!m.E || !m.nu) return fail(FE_ERR_INVALID_ARG, "materials arrays are NULL");
+  for (int i = 0; i < m.n_phases; ++i) {
+    if (!(std::isfinite(m.E[i]) && m.E[i] > 0.0))
+      return fail(FE_ERR_INVALID_ARG, "phase %d: Young's modulus must be finite and > 0", i);
+    if (!(std::isfinite(m.nu[i]) && m.nu[i] > -1.0 && m.nu[i] < 0.5))
+      return fail(FE_ERR_INVALID_ARG, "phase %d: Poisson ratio must be in (-1, 0.5)", i);
+  }
+  return FE_OK;
+}
+
+// Frobenius norm of a symmetric tensor given in Voigt order (off-diagonals twice).
+static double frob(const double* s) {
+  return std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
+}
+
+template <typename T>
+static const Tables<T>& tables(const fe_plan* p);
+template <>
+const Tables<float>& tables<float>(const fe_plan* p) { return p->t32; }
+template <>
+const Tables<double>& tables<double>(const fe_plan* p) { return p->t64; }
+
+template <typename T>
+static WaveTables<T> wave_tables(const fe_plan* p) {
+  const Tables<T>& t = tables<T>(p);
+  return WaveTables<T>{t.wave[0], t.wave[1], t.wave[2]};
+}
+
+// eta and <sigma> of the current strain (float64 arithmetic from a strain of
+// storage type TS), via the spectral 6-component path for MS or the
+// corner/backward stencil otherwise.  Requires a float64 workspace for MS when
+// TS is float (allocated and released here).
+template <typename TS>
+static fe_status verify_fp64(fe_plan* p, const TS* eps, const uint8_t* phase, double* eta_out) {
+  hipStream_t s = p->stream;
+  const Dims d = p->d;
+  if (p->displacement) {
+    launch_verify_div<TS>(eps, phase, p->coef64, p->partials, p->div_blocks, d, p->op, s);
+    launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
+    HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double ms[6];
+    for (int i = 0; i < 6; ++i) ms[i] = p->h_red[1 + i] / (double)d.N;
+    *eta_out = std::sqrt(p->h_red[0] / (double)d.N) / frob(ms);
+    return FE_OK;
+  }
+  double *e64 = nullptr, *r64 = nullptr;
+  cpx<double>* s64 = nullptr;
+  const size_t spec = (size_t)d.H * d.ny * d.nx;
+  if (hipMalloc(&e64, 6 * (size_t)d.N * 8) != hipSuccess || hipMalloc(&r64, 6 * (size_t)d.N * 8) != hipSuccess ||
+      hipMalloc(&s64, 6 * spec * sizeof(cpx<double>)) != hipSuccess) {
+    if (e64) (void)hipFree(e64);
+    if (r64) (void)hipFree(r64);
+    (void)hipGetLastError();
+    *eta_out = NAN;
+    return FE_OK;
+  }
+  Launch<double>::convert_to(e64, eps, sizeof(TS) == 8, 6 * d.N, s);
+  Launch<double>::tau6(e64, phase, p->coef64, r64, 1, p->partials, p->div_blocks, d, s);
+  launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
+  const Tables<double>& t = p->t64;
+  Launch<double>::zr2c(r64, s64, 6, d, t.tw[2], p->plan_z, s);
+  Launch<double>::yfft(s64, 6, d, t.tw[1], p->plan_y, 0, s);
+  Launch<double>::xeta6(s64, d, t.tw[0], p->plan_x, wave_tables<double>(p), p->partials2, 0, p->op, s);
+  const int nl = std::max(1, TileCap<double>::CAP6 / (6 * d.nx));
+  const int nblk = (d.H * d.ny + nl - 1) / nl;
+  launch_reduce(p->partials2, nblk, 1, p->red + 8, s);
+  HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  (void)hipFree(e64);
+  (void)hipFree(r64);
+  (void)hipFree(s64);
+  double ms[6];
+  for (int i = 0; i < 6; ++i) ms[i] = p->h_red[1 + i] / (double)d.N;
+  *eta_out = std::sqrt(p->h_red[8]) / ((double)d.N * frob(ms));
+  return FE_OK;
+}
+
+template <typename T>
+static int xeta_blocks(const Dims& d) {
+  const int nl = std::max(1, TileCap<T>::CAP6 / (6 * d.nx));
+  return (d.H * d.ny + nl - 1) / nl;
+}
+
+template <typename T>
+static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials& mat, const double* macro, double tol,
+                            const void* strain_init, fe_result* out) {
+  hipStream_t s = p->stream;
+  const Dims d = p->d;
+  const long long N = d.N;
+  const Tables<T>& tb = tables<T>(p);
+  const WaveTables<T> wt = wave_tables<T>(p);
+
+  // per-phase constants (float64 on the host, rounded to T for the kernels)
+  const RefMedium ref = reference_medium(p, mat);
+  std::vector<PhaseCoef<double>> c64 = phase_coefs(mat, ref);
+  std::vector<PhaseCoef<T>> cT(c64.size());
+  for (size_t i = 0; i < c64.size(); ++i) {
+    cT[i].lam = T(c64[i].lam);
+    cT[i].mu = T(c64[i].mu);
+    cT[i].dlam = T(c64[i].dlam);
+    cT[i].dmu = T(c64[i].dmu);
+    cT[i].ak = T(c64[i].ak);
+    cT[i].am = T(c64[i].am);
+    cT[i].pad0 = cT[i].pad1 = T(0);
+  }
+  HIP_TRY(hipMemcpyAsync(p->coef, cT.data(), cT.size() * sizeof(PhaseCoef<T>), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(p->coef64, c64.data(), c64.size() * sizeof(PhaseCoef<double>), hipMemcpyHostToDevice, s));
+  const PhaseCoef<T>* coef = static_cast<const PhaseCoef<T>*>(p->coef);
+
+  GreenConst<T> g;
+  g.lam0 = T(ref.lam0);
+  g.mu0 = T(ref.mu0);
+  g.cr = T((ref.lam0 + ref.mu0) / (ref.lam0 + 2.0 * ref.mu0));
+  g.s1 = T(1.0 / (2.0 * ref.mu0));
+  g.s2 = T(ref.lam0 / (2.0 * ref.mu0 * (3.0 * ref.lam0 + 2.0 * ref.mu0)));
+  g.inv_n = T(1.0 / (double)N);
+  for (int i = 0; i < 6; ++i) g.macro[i] = T(macro[i]);
+
+  // phase labels must index the table
+  HIP_TRY(hipMemsetAsync(p->flag, 0, sizeof(int), s));
+  Launch<T>::check_phase(phase, N, mat.n_phases, p->flag, s);
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, p->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hflag) return fail(FE_ERR_INVALID_ARG, "phase map holds a label >= n_phases (%d)", mat.n_phases);
+
+  T* eps = static_cast<T*>(out->strain);
+  if (!eps) {
+    if (!p->eps_ws) HIP_TRY(dmalloc(p, &p->eps_ws, 6 * (size_t)N * sizeof(T)));
+    eps = static_cast<T*>(p->eps_ws);
+  }
+  if (strain_init) {
+    if (strain_init != eps)
+      HIP_TRY(hipMemcpyAsync(eps, strain_init, 6 * (size_t)N * sizeof(T), hipMemcpyDeviceToDevice, s));
+  } else {
+    Launch<T>::fill_macro(eps, N, macro, s);
+  }
+
+  T* R = static_cast<T*>(p->R);
+  cpx<T>* S = static_cast<cpx<T>*>(p->S);
+  const int ncomp = p->displacement ? 3 : 6;
+  const int accel = p->scheme == FE_ACCELERATED;
+  const int max_iter = p->opt.max_iter;
+  const int every = p->opt.check_every;
+  const int xblk = xeta_blocks<T>(d);
+
+  HIP_TRY(hipEventRecord(p->ev0, s));
+  fe_status status = FE_NOT_CONVERGED;
+  double eta = NAN, prev_eta = INFINITY, mean[6] = {0, 0, 0, 0, 0, 0};
+  int rising = 0, k = 0;
+  for (k = 0;; ++k) {
+    const bool check = (k % every == 0) || k == max_iter;
+    if (p->displacement) {
+      Launch<T>::div(eps, phase, coef, R, p->partials, p->div_blocks, d, p->op, s);
+      if (check) launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
+    } else if (check) {
+      Launch<T>::tau6(eps, phase, coef, R, 1, p->partials, p->div_blocks, d, s);
+      launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
+      Launch<T>::zr2c(R, S, 6, d, tb.tw[2], p->plan_z, s);
+      Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 0, s);
+      Launch<T>::xeta6(S, d, tb.tw[0], p->plan_x, wt, p->partials2, xblk, p->op, s);
+      launch_reduce(p->partials2, xblk, 1, p->red + 8, s);
+    }
+    if (check) {
+      HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      for (int i = 0; i < 6; ++i) mean[i] = p->h_red[1 + i] / (double)N;
+      const double nrm = frob(mean);
+      eta = p->displacement ? std::sqrt(p->h_red[0] / (double)N) / nrm : std::sqrt(p->h_red[8]) / ((double)N * nrm);
+      if (out->eta_history && k < out->history_capacity) out->eta_history[k] = eta;
+      if (!std::isfinite(eta)) {
+        status = FE_DIVERGED;
+        break;
+      }
+      if (eta <= tol) {
+        status = FE_OK;
+        break;
+      }
+      if (k >= max_iter) {
+        status = FE_NOT_CONVERGED;
+        break;
+      }
+      rising = eta > prev_eta ? rising + 1 : 0;
+      prev_eta = eta;
+      if (p->opt.diverge_window > 0 && rising >= p->opt.diverge_window) {
+        status = FE_DIVERGED;
+        break;
+      }
+    }
+    if (p->displacement) {
+      Launch<T>::zr2c(R, S, 3, d, tb.tw[2], p->plan_z, s);
+      Launch<T>::yfft(S, 3, d, tb.tw[1], p->plan_y, 0, s);
+      Launch<T>::xgreen3(S, d, tb.tw[0], p->plan_x, wt, g, p->op, s);
+      Launch<T>::yfft(S, 3, d, tb.tw[1], p->plan_y, 1, s);
+      Launch<T>::zc2r(S, R, 3, d, tb.tw[2], p->plan_z, s);
+      Launch<T>::grad_update(R, eps, phase, coef, g, d, p->op, accel, s);
+    } else {
+      Launch<T>::tau6(eps, phase, coef, R, 0, nullptr, p->div_blocks, d, s);
+      Launch<T>::zr2c(R, S, 6, d, tb.tw[2], p->plan_z, s);
+      Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 0, s);
+      Launch<T>::xgreen6(S, d, tb.tw[0], p->plan_x, wt, g, p->op, s);
+      Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 1, s);
+      Launch<T>::zc2r(S, R, 6, d, tb.tw[2], p->plan_z, s);
+      Launch<T>::update6(R, eps, phase, coef, d, accel, s);
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipEventRecord(p->ev1, s));
+  HIP_TRY(hipEventSynchronize(p->ev1));
+  float ms_elapsed = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms_elapsed, p->ev0, p->ev1));
+  HIP_TRY(hipGetLastError());
+
+  if (out->stress) Launch<T>::stress(eps, phase, coef, static_cast<T*>(out->stress), N, s);
+  double ev = eta;
+  if (sizeof(T) == 4) {
+    fe_status vs = verify_fp64<T>(p, eps, phase, &ev);
+    if (vs != FE_OK) return vs;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  out->iterations = k;
+  out->eta = eta;
+  out->eta_verify_fp64 = ev;
+  out->seconds = ms_elapsed * 1e-3;
+  for (int i = 0; i < 6; ++i) out->mean_stress[i] = mean[i];
+  if (status == FE_NOT_CONVERGED)
+    fail(status, "not converged after %d iterations (eta = %.3e, tol = %.3e)", k, eta, tol);
+  else if (status == FE_DIVERGED)
+    fail(status, "diverged at iteration %d (eta = %.3e)", k, eta);
+  return status;
+}
+
+extern "C" fe_status fe_solve(fe_plan* p, const uint8_t* phase, fe_materials materials, const double macro_strain[6],
+                              double tol, const void* strain_init, fe_result* out) {
+  if (!p) return fail(FE_ERR_INVALID_ARG, "plan is NULL");
+  if (!phase) return fail(FE_ERR_INVALID_ARG, "phase is NULL");
+  if (!macro_strain) return fail(FE_ERR_INVALID_ARG, "macro_strain is NULL");
+  if (!out) return fail(FE_ERR_INVALID_ARG, "out is NULL");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FE_ERR_INVALID_ARG, "tol must be finite and > 0");
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(macro_strain[i])) return fail(FE_ERR_INVALID_ARG, "macro_strain[%d] is not finite", i);
+  if (out->history_capacity < 0) return fail(FE_ERR_INVALID_ARG, "history_capacity < 0");
+  if (out->history_capacity > 0 && !out->eta_history)
+    return fail(FE_ERR_INVALID_ARG, "eta_history is NULL with a positive capacity");
+  fe_status st = validate_materials(materials);
+  if (st != FE_OK) return st;
+  HIP_TRY(hipSetDevice(p->device));
+  if (p->opt.precision == FE_FP64)
+    return solve_impl<double>(p, phase, materials, macro_strain, tol, strain_init, out);
+  return solve_impl<float>(p, phase, materials, macro_strain, tol, strain_init, out);
+}
+
+extern "C" fe_status fe_effective_stiffness(fe_plan* p, const uint8_t* phase, fe_materials materials, double tol,
+                                            double C_voigt[36], int32_t iterations[6]) {
+  if (!C_voigt) return fail(FE_ERR_INVALID_ARG, "C_voigt is NULL");
+  fe_status worst = FE_OK;
+  for (int J = 0; J < 6; ++J) {
+    double e[6] = {0, 0, 0, 0, 0, 0};
+    e[J] = 1.0;
+    fe_result r;
+    std::memset(&r, 0, sizeof r);
+    fe_status st = fe_solve(p, phase, materials, e, tol, nullptr, &r);
+    if (st < 0) return st;
+    if (st > worst) worst = st;
+    for (int I = 0; I < 6; ++I) C_voigt[6 * I + J] = J < 3 ? r.mean_stress[I] : 0.5 * r.mean_stress[I];
+    if (iterations) iterations[J] = r.iterations;
+  }
+  return worst;
+}
+
+extern "C" const char* fe_status_string(fe_status s) {
+  switch (s) {
+    case FE_OK: return "FE_OK";
+    case FE_NOT_CONVERGED: return "FE_NOT_CONVERGED";
+    case FE_DIVERGED: return "FE_DIVERGED";
+    case FE_ERR_INVALID_ARG: return "FE_ERR_INVALID_ARG";
+    case FE_ERR_UNSUPPORTED: return "FE_ERR_UNSUPPORTED";
+    case FE_ERR_OOM: return "FE_ERR_OOM";
+    case FE_ERR_DEVICE: return "FE_ERR_DEVICE";
+  }
+  return "FE_UNKNOWN_STATUS";
+}
+
+extern "C" const char* fe_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,105 @@
+// Host-side launchers of the gfx950 kernels (one instantiation per real type).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fe_device.h"
+
+namespace fe {
+
+enum Op { OP_MS = 0, OP_WP = 1, OP_ROT = 2 };
+
+struct Dims {
+  int nx, ny, nz, H;  // H = nz/2 + 1 (half spectrum along z)
+  long long N;        // nx*ny*nz
+};
+
+// Per-phase constants derived on the host in float64 from (E, nu) and C0.
+template <typename T>
+struct PhaseCoef {
+  T lam, mu;    // C = lam I(x)I + 2 mu Id
+  T dlam, dmu;  // C - C0
+  T ak, am;     // 2 kappa0/(kappa+kappa0), 2 mu0/(mu+mu0): (C+C0)^-1 C0 times 2
+  T pad0, pad1;
+};
+
+// Reference-medium constants of the Green operator.
+template <typename T>
+struct GreenConst {
+  T lam0, mu0;
+  T cr;       // (lam0 + mu0)/(lam0 + 2 mu0)
+  T s1, s2;   // (C0)^-1 : tau = s1 tau - s2 tr(tau) I
+  T inv_n;    // 1/N, folded into the Green step so inverse transforms are unnormalised
+  T macro[6]; // eps_bar (tensor Voigt order)
+};
+
+// Per-axis wave tables, 2 reals per index m in [0, n):
+//   ROT: (sin(pi m'/n), cos(pi m'/n));  WP: (cos q - 1, sin q);  MS: (q, 1 if Nyquist else 0)
+template <typename T>
+struct WaveTables {
+  const T* x;
+  const T* y;
+  const T* z;
+};
+
+template <typename T>
+struct Launch {
+  // eps^0 = eps_bar
+  static void fill_macro(T* eps, long long N, const double* macro, hipStream_t s);
+  static void convert_to(T* dst, const void* src, int src_is_double, long long n, hipStream_t s);
+  static void check_phase(const uint8_t* phase, long long N, int n_phases, int* flag, hipStream_t s);
+
+  // Pipeline for the WP and ROT operators (displacement form).
+  static void div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, double* partials,
+                  int nblocks, Dims d, int op, hipStream_t s);
+  static void grad_update(const T* U, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef,
+                          GreenConst<T> g, Dims d, int op, int accelerated, hipStream_t s);
+  static void xgreen3(cpx<T>* S, Dims d, const cpx<T>* twx, uint32_t planx, WaveTables<T> wt,
+                      GreenConst<T> g, int op, hipStream_t s);
+
+  // Pipeline for every operator (6-component form).
+  static void tau6(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* out, int write_sigma,
+                   double* partials, int nblocks, Dims d, hipStream_t s);
+  static void xgreen6(cpx<T>* S, Dims d, const cpx<T>* twx, uint32_t planx, WaveTables<T> wt,
+                      GreenConst<T> g, int op, hipStream_t s);
+  static void xeta6(const cpx<T>* S, Dims d, const cpx<T>* twx, uint32_t planx, WaveTables<T> wt,
+                    double* partials, int nblocks, int op, hipStream_t s);
+  static void update6(const T* e, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, Dims d,
+                      int accelerated, hipStream_t s);
+
+  // Strided FFT passes.
+  static void zr2c(const T* R, cpx<T>* S, int ncomp, Dims d, const cpx<T>* twz, uint32_t planz, hipStream_t s);
+  static void zc2r(const cpx<T>* S, T* R, int ncomp, Dims d, const cpx<T>* twz, uint32_t planz, hipStream_t s);
+  static void yfft(cpx<T>* S, int ncomp, Dims d, const cpx<T>* twy, uint32_t plany, int inverse, hipStream_t s);
+
+  static void stress(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* sigma, long long N,
+                     hipStream_t s);
+  static int set_kernel_attributes();
+};
+
+// float64 verification of eta from a strain of storage type TS (ROT, WP).
+template <typename TS>
+void launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* partials,
+                       int nblocks, Dims d, int op, hipStream_t s);
+
+void launch_reduce(const double* partials, int nblocks, int nv, double* out, hipStream_t s);
+
+// Tile sizes (elements of the LDS tile) per real type.
+template <typename T>
+struct TileCap;
+template <>
+struct TileCap<float> {
+  static constexpr int CAP = 8192;   // 64 KiB of complex float
+  static constexpr int CAP6 = 8192;
+};
+template <>
+struct TileCap<double> {
+  static constexpr int CAP = 4096;   // 64 KiB of complex double
+  static constexpr int CAP6 = 6144;  // 96 KiB: six components of a 1024-long line
+};
+
+constexpr int kThreads = 256;
+constexpr int kMaxReduceBlocks = 4096;
+
+}  // namespace fe

@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports every symbol include/fe.h declares;
+argument checks that run before any device call (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1412_8398_amd as fe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    with open(os.path.join(ROOT, "include", "fe.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    for m in re.finditer(r"\b(fe_[a-z0-9_]+)\s*\(", text):
+        names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(fe.library_path()):
+        pytest.fail("libfe.so is not built (run `python -m paper_1412_8398_amd.build`)")
+    return fe.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for must in ("fe_plan_create", "fe_plan_destroy", "fe_solve", "fe_effective_stiffness",
+                 "fe_status_string", "fe_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), f"libfe.so does not export {name}"
+
+
+def test_status_strings(lib):
+    assert fe.status_string(fe.FE_OK) == "FE_OK"
+    assert fe.status_string(fe.FE_ERR_UNSUPPORTED) == "FE_ERR_UNSUPPORTED"
+    assert fe.status_string(123) == "FE_UNKNOWN_STATUS"
+
+
+def _create(lib, nx, ny, nz, disc=2, scheme=1, **kw):
+    opt = fe.FePlanOptions()
+    lib.fe_plan_options_default(C.byref(opt))
+    for k, v in kw.items():
+        setattr(opt, k, v)
+    h = C.c_void_p()
+    s = lib.fe_plan_create(fe.FeGrid(nx, ny, nz), disc, scheme, C.byref(opt), C.byref(h))
+    return s, h
+
+
+@pytest.mark.parametrize("dims,status", [
+    ((14, 16, 16), fe.FE_ERR_UNSUPPORTED),   # 14 = 2 * 7
+    ((16, 15, 16), fe.FE_ERR_UNSUPPORTED),   # odd
+    ((2048, 16, 16), fe.FE_ERR_UNSUPPORTED),  # above 1024
+    ((2, 16, 16), fe.FE_ERR_UNSUPPORTED),
+    ((0, 16, 16), fe.FE_ERR_INVALID_ARG),
+    ((-8, 16, 16), fe.FE_ERR_INVALID_ARG),
+])
+def test_plan_rejects_bad_grids_before_device_work(lib, dims, status):
+    s, h = _create(lib, *dims)
+    assert s == status
+    assert not h.value
+    assert "grid dimension" in fe.last_error()
+
+
+def test_plan_rejects_bad_options(lib):
+    assert _create(lib, 16, 16, 16, disc=7)[0] == fe.FE_ERR_INVALID_ARG
+    assert _create(lib, 16, 16, 16, scheme=3)[0] == fe.FE_ERR_INVALID_ARG
+    assert _create(lib, 16, 16, 16, precision=5)[0] == fe.FE_ERR_INVALID_ARG
+    assert _create(lib, 16, 16, 16, check_every=0)[0] == fe.FE_ERR_INVALID_ARG
+    assert _create(lib, 16, 16, 16, ref_rule=1, E0=-1.0)[0] == fe.FE_ERR_INVALID_ARG
+    assert _create(lib, 16, 16, 16, ref_rule=1, E0=1.0, nu0=0.5)[0] == fe.FE_ERR_INVALID_ARG
+    assert _create(lib, 16, 16, 16, scheme=0, ds_beta=0.0)[0] == fe.FE_ERR_INVALID_ARG
+    assert _create(lib, 16, 16, 16, struct_size=4)[0] == fe.FE_ERR_INVALID_ARG
+
+
+def test_solve_rejects_null_plan_and_bad_arguments(lib):
+    E = (C.c_double * 2)(1.0, 2.0)
+    nu = (C.c_double * 2)(0.3, 0.3)
+    m = fe.FeMaterials(2, E, nu)
+    macro = (C.c_double * 6)(1, 0, 0, 0, 0, 0)
+    r = fe.FeResult()
+    assert lib.fe_solve(None, None, m, macro, 1e-6, None, C.byref(r)) == fe.FE_ERR_INVALID_ARG
+    assert lib.fe_effective_stiffness(None, None, m, 1e-6, None, None) == fe.FE_ERR_INVALID_ARG

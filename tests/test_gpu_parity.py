@@ -1,0 +1,188 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle,
+element by element at equal iteration index, plus invariants and error paths.
+
+Tolerances
+  FP64: relative L2 error of the strain field <= 1e-12 after k iterations;
+        eta^k within 1e-10 relative plus 1e-14 absolute (both sides float64,
+        different summation orders; eta is a norm of a residual that is a
+        difference of O(1) stresses, so it carries ~1e-15 absolute rounding
+        noise once it is small).
+  FP32: relative L2 error <= 2e-5 after a few iterations (single-precision
+        FFTs of length <= 768 with float32 twiddles: ~1e-6 per transform, a
+        handful of transforms per iteration); eta^k relative error <= 1e-3.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from microstructure import laminate, sphere_inclusion, voronoi_cells
+
+torch = pytest.importorskip("torch")
+import paper_1412_8398_amd as fe  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+OPS = {"MS": "MS", "W": "W", "R": "R"}
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _run(phase, E, nu, macro, op, scheme, precision, k=None, tol=None, strain_init=None, **plan_kw):
+    nz, ny, nx = phase.shape
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    max_iter = k if k is not None else plan_kw.pop("max_iter", 2000)
+    with fe.Plan((nx, ny, nz), green=op, scheme=scheme, precision=precision, max_iter=max_iter, **plan_kw) as plan:
+        eps = torch.empty((6, nz, ny, nx), dtype=dt, device="cuda")
+        init = None if strain_init is None else _dev(strain_init.astype(np.float64 if precision == "fp64" else np.float32))
+        res = plan.solve(_dev(phase), E, nu, macro, tol if tol is not None else 1e-300, strain_init=init,
+                         strain=eps, history=max_iter + 1)
+        torch.cuda.synchronize()
+    return res, eps.cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _three_phase(shape, seed=7):
+    ph, _, _ = voronoi_cells(shape, 10, 3, seed)
+    return ph, [1.0, 5.0, 50.0], [0.2, 0.3, 0.35]
+
+
+MACRO = [0.7, -0.2, 0.3, 0.15, -0.4, 0.25]
+
+
+def test_config1_direct_rotated_fp64_full_solve():
+    """32^3 centred sphere (3112 voxels), E = 10 / 1, nu = 0.3, eps_bar = e1 (x) e1,
+    DS with the rotated operator, tol 1e-10: same iteration count, eta history,
+    fields and mean stress as the oracle."""
+    L = 32
+    phase = sphere_inclusion((L, L, L), (16, 16, 16), 9.0)
+    assert int(phase.sum()) == 3112
+    E, nu, macro = [1.0, 10.0], [0.3, 0.3], [1, 0, 0, 0, 0, 0]
+    ref = O.solve(phase, E, nu, macro, op="R", scheme="DS", tol=1e-10, max_iter=500)
+    res, eps = _run(phase, E, nu, macro, "R", "DS", "fp64", tol=1e-10, max_iter=500)
+    assert res.status == fe.FE_OK
+    assert res.iterations == ref.iterations
+    assert np.allclose(res.eta_history, ref.eta_history, rtol=1e-10, atol=1e-14)
+    assert _rel(eps, O.tensor_to_voigt(ref.eps)) < 1e-12
+    assert np.allclose(res.mean_stress, O.tensor_to_voigt(ref.mean_stress), rtol=1e-12, atol=1e-14)
+    assert res.eta_verify_fp64 == res.eta
+
+
+@pytest.mark.parametrize("scheme", ["DS", "AS"])
+@pytest.mark.parametrize("op", ["MS", "W", "R"])
+def test_equal_iteration_parity_fp64(op, scheme):
+    shape = (24, 16, 36)  # (nz, ny, nx): radix 8,3 / 8,2 / 4,3,3
+    phase, E, nu = _three_phase(shape)
+    k = 4
+    ref = O.solve(phase, E, nu, MACRO, op=op, scheme=scheme, tol=1e-300, max_iter=k)
+    res, eps = _run(phase, E, nu, MACRO, op, scheme, "fp64", k=k)
+    assert res.iterations == k and res.status == fe.FE_NOT_CONVERGED
+    assert _rel(eps, O.tensor_to_voigt(ref.eps)) < 1e-12
+    assert np.allclose(res.eta_history, ref.eta_history, rtol=1e-10, atol=1e-14)
+
+
+@pytest.mark.parametrize("scheme", ["DS", "AS"])
+@pytest.mark.parametrize("op", ["MS", "W", "R"])
+def test_equal_iteration_parity_fp32(op, scheme):
+    shape = (24, 16, 36)
+    phase, E, nu = _three_phase(shape)
+    k = 4
+    ref = O.solve(phase, E, nu, MACRO, op=op, scheme=scheme, tol=1e-300, max_iter=k)
+    res, eps = _run(phase, E, nu, MACRO, op, scheme, "fp32", k=k)
+    assert _rel(eps, O.tensor_to_voigt(ref.eps)) < 2e-5
+    assert np.allclose(res.eta_history, ref.eta_history, rtol=1e-3, atol=0)
+    # the float64 verification residual of the returned strain
+    want = O.equilibrium_norm(op, O.homogenization.apply_phasewise(
+        [O.stiffness_tensor(l, m) for l, m in zip(*O.lame_from_young(E, nu))], phase, O.voigt_to_tensor(eps)))
+    assert abs(res.eta_verify_fp64 - want) <= 1e-9 * want
+
+
+@pytest.mark.parametrize("shape", [(384, 12, 36), (12, 768, 24)])
+def test_ragged_tiles_parity_fp64(shape):
+    """Grids whose FFT passes end in partial tiles (z-pass column tiles, y-pass
+    column tiles, x-pass line blocks)."""
+    phase, E, nu = _three_phase(shape, seed=11)
+    k = 3
+    ref = O.solve(phase, E, nu, MACRO, op="R", scheme="AS", tol=1e-300, max_iter=k)
+    res, eps = _run(phase, E, nu, MACRO, "R", "AS", "fp64", k=k)
+    assert _rel(eps, O.tensor_to_voigt(ref.eps)) < 1e-12
+
+
+def test_warm_start_parity_fp64(rng):
+    shape = (16, 24, 12)
+    phase, E, nu = _three_phase(shape, seed=3)
+    start = O.tensor_to_voigt(O.voigt_to_tensor(rng.standard_normal((6,) + shape)))
+    k = 3
+    for op in ("R", "MS"):
+        ref = O.solve(phase, E, nu, MACRO, op=op, scheme="AS", tol=1e-300, max_iter=k,
+                      eps_init=O.voigt_to_tensor(start))
+        res, eps = _run(phase, E, nu, MACRO, op, "AS", "fp64", k=k, strain_init=start)
+        assert _rel(eps, O.tensor_to_voigt(ref.eps)) < 1e-12
+        assert np.allclose(res.eta_history, ref.eta_history, rtol=1e-10, atol=1e-14)
+
+
+@pytest.mark.parametrize("op", ["MS", "W", "R"])
+def test_homogeneous_medium_converges_in_one_step(op, rng):
+    shape = (8, 12, 16)
+    phase = (rng.random(shape) < 0.5).astype(np.uint8)
+    start = rng.standard_normal((6,) + shape)
+    res, eps = _run(phase, [2.0, 2.0], [0.3, 0.3], MACRO, op, "AS", "fp64", k=1, strain_init=start)
+    assert np.allclose(eps, np.array(MACRO)[:, None, None, None], atol=1e-13)
+
+
+@pytest.mark.parametrize("op,layers", [("R", [3, 9]), ("W", [5, 7]), ("MS", [4, 8])])
+def test_laminate_exact_on_gpu(op, layers):
+    labels = np.array([1] * layers[0] + [0] * layers[1], dtype=np.uint8)
+    shape = (6, 8, sum(layers))
+    phase = laminate(shape, labels)
+    E, nu = [1.0, 7.0], [0.3, 0.2]
+    res, eps = _run(phase, E, nu, MACRO, op, "AS", "fp64", tol=1e-13, max_iter=2000)
+    assert res.status == fe.FE_OK
+    ref = O.solve(phase, E, nu, MACRO, op=op, scheme="AS", tol=1e-13, max_iter=2000)
+    assert np.max(np.abs(eps - O.tensor_to_voigt(ref.eps))) < 1e-10
+
+
+def test_effective_stiffness_matches_oracle():
+    phase = sphere_inclusion((12, 12, 12), (6, 6, 6), 3.5)
+    E, nu = [1.0, 20.0], [0.3, 0.2]
+    want, its_ref = O.effective_stiffness(phase, E, nu, op="R", scheme="AS", tol=1e-10)
+    with fe.Plan(12, green="R", scheme="AS", precision="fp64") as plan:
+        Cv, its, st = plan.effective_stiffness(_dev(phase), E, nu, 1e-10)
+    assert st == fe.FE_OK
+    assert its == its_ref
+    assert np.allclose(Cv, want, rtol=1e-11, atol=1e-12)
+
+
+def test_bad_phase_label_is_reported():
+    phase = np.zeros((8, 8, 8), dtype=np.uint8)
+    phase[3, 4, 5] = 2
+    with fe.Plan(8, green="R", scheme="AS", precision="fp32") as plan:
+        with pytest.raises(fe.FeError) as ei:
+            plan.solve(_dev(phase), [1.0, 2.0], [0.3, 0.3], MACRO, 1e-6)
+    assert ei.value.status == fe.FE_ERR_INVALID_ARG
+
+
+def test_iteration_cap_returns_last_iterate():
+    phase = sphere_inclusion((16, 16, 16), (8, 8, 8), 5.0)
+    res, eps = _run(phase, [1.0, 100.0], [0.3, 0.3], MACRO, "R", "DS", "fp32", tol=1e-12, max_iter=5)
+    assert res.status == fe.FE_NOT_CONVERGED and res.iterations == 5
+    assert np.isfinite(eps).all()
+
+
+def test_direct_scheme_below_half_reports_divergence():
+    phase = sphere_inclusion((8, 8, 8), (4, 4, 4), 2.6)
+    res, _ = _run(phase, [1.0, 50.0], [0.3, 0.3], [1, 0, 0, 0, 0, 0], "R", "DS", "fp64", tol=1e-12,
+                  max_iter=3000, ds_beta=0.45, diverge_window=30)
+    assert res.status == fe.FE_DIVERGED
+
+
+def test_runs_are_bitwise_deterministic():
+    phase, E, nu = _three_phase((32, 32, 32), seed=5)
+    a_res, a = _run(phase, E, nu, MACRO, "R", "AS", "fp32", k=6)
+    b_res, b = _run(phase, E, nu, MACRO, "R", "AS", "fp32", k=6)
+    assert np.array_equal(a, b)
+    assert list(a_res.eta_history) == list(b_res.eta_history)
