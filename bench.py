@@ -1,0 +1,215 @@
+"""Benchmark of the Lippmann-Schwinger FFT iteration on one MI355X.
+
+Workload (one "step" = one full iteration: divergence stencil, forward 3D
+transform, Green operator, inverse 3D transform, strain update, float64
+equilibrium-norm reduction):
+  512^3 sphere-Boolean microstructure (Poisson spheres of radius 6 voxels,
+  target volume fraction 0.25, seed 20141230), inclusion/matrix Young's
+  moduli 10 / 1, nu = 0.3 in both phases, macroscopic shear eps_12 = 1,
+  accelerated scheme with the rotated-grid Green operator, float32 fields,
+  float64 reductions; reference medium by the geometric-mean rule.
+
+Prints one JSON line.  Also reports the time to eta <= 1e-6 from the plain
+start (eps^0 = eps_bar) and, on rank 0, the FP64 CPU oracle's rate on a bounded
+sample of the same recipe.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "voxel-iter/s & time to 1e-6 equilibrium at 512^3: plain vs learned warm start"
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
+
+RECIPE = dict(radius=6.0, fraction=0.25, E=(1.0, 10.0), nu=(0.3, 0.3), seed=20141230)
+MACRO = (0.0, 0.0, 0.0, 0.0, 0.0, 1.0)  # eps_12 = 1 (tensor Voigt order)
+
+
+def make_phase(L: int):
+    from microstructure import boolean_spheres
+
+    phase, info = boolean_spheres((L, L, L), RECIPE["radius"], RECIPE["fraction"], RECIPE["seed"])
+    return phase, info
+
+
+def pass_bytes(L: int, elem: int = 4):
+    """Algorithmic HBM bytes of one launch of each pass (displacement form,
+    3-component spectra, accelerated scheme), for an L^3 grid."""
+    N = L ** 3
+    H = L // 2 + 1
+    spec = 3 * H * L * L * 2 * elem        # 3 half spectra along z, complex
+    real3 = 3 * N * elem                   # 3 real planes (divergence / displacement)
+    strain = 6 * N * elem
+    return {
+        "pointwise": strain + N + real3,              # read eps, phase; write D
+        "zfwd": real3 + spec,                         # read D; write half spectra
+        "yfwd": 2 * spec,                             # read + write in place
+        "xgreen": 2 * spec,
+        "yinv": 2 * spec,
+        "zinv": spec + real3,                         # read half spectra; write U
+        "update": real3 + strain + N + strain,        # read U, eps, phase; write eps
+    }
+
+
+def cpu_baseline(L_sample: int, iters: int):
+    """The FP64 oracle on the host cores: AS with the rotated operator on an
+    L_sample^3 sample of the same recipe, `iters` iterations."""
+    workers = min(16, os.cpu_count() or 1)
+    os.environ["ORACLE_WORKERS"] = str(workers)
+    import oracle as O
+    from microstructure import boolean_spheres
+
+    phase, _ = boolean_spheres((L_sample,) * 3, RECIPE["radius"], RECIPE["fraction"], RECIPE["seed"])
+    O.solve(phase, list(RECIPE["E"]), list(RECIPE["nu"]), MACRO, op="R", scheme="AS", tol=1e-300, max_iter=1)
+    t0 = time.perf_counter()
+    O.solve(phase, list(RECIPE["E"]), list(RECIPE["nu"]), MACRO, op="R", scheme="AS", tol=1e-300, max_iter=iters)
+    dt = time.perf_counter() - t0
+    return {
+        "value": L_sample ** 3 * iters / dt,
+        "unit": "voxel-iter/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": f"{L_sample}^3 of the same recipe, {iters} iterations (+1 eta evaluation), FP64 NumPy/SciPy, "
+                  f"{dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tti", action="store_true", help="skip the time-to-tolerance solve")
+    ap.add_argument("--cpu-sample", type=int, default=96)
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (reference kernel for HBM counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
+                                   "supported (one solve per GPU, no inter-GPU exchange)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1412_8398_amd as fe
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    L = args.size
+    phase_np, info = make_phase(L)
+    phase = torch.from_numpy(phase_np).cuda()
+    eps = torch.empty((6, L, L, L), dtype=torch.float32, device="cuda")
+    N = L ** 3
+    E, nu = list(RECIPE["E"]), list(RECIPE["nu"])
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # warmup
+    with fe.Plan(L, green="R", scheme="AS", precision="fp32", max_iter=max(args.warmup, 1)) as plan:
+        plan.solve(phase, E, nu, MACRO, 1e-300, strain=eps)
+    torch.cuda.synchronize()
+
+    # timed: exactly K iterations (tol below reach), per-pass HIP-event timing on the plan's stream
+    K = args.steps
+    with fe.Plan(L, green="R", scheme="AS", precision="fp32", max_iter=K, timing=True) as plan:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = plan.solve(phase, E, nu, MACRO, 1e-300, strain=eps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    wall = t1 - t0
+    value = N * K / wall
+
+    pb = pass_bytes(L)
+    passes = {}
+    for name, nbytes in pb.items():
+        launches = res.pass_launches[name]
+        if launches:
+            avg = res.pass_seconds[name] / launches
+            passes[name] = {"avg_ms": avg * 1e3, "launches": launches, "gbs": nbytes / avg / 1e9,
+                            "bytes_per_launch": nbytes}
+    dom = max(passes, key=lambda n: passes[n]["avg_ms"] * passes[n]["launches"])
+    roof = {
+        "bound": "hbm",
+        "kernel": dom,
+        "achieved": round(passes[dom]["gbs"], 1),
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": round(passes[dom]["gbs"] / PEAK_HBM_GBS, 4),
+        "traffic": None,
+    }
+    step_bytes = sum(pb.values())
+    iter_gbs = step_bytes * K / wall / 1e9
+
+    tti = None
+    if not args.no_tti:
+        with fe.Plan(L, green="R", scheme="AS", precision="fp32", max_iter=2000) as plan:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r2 = plan.solve(phase, E, nu, MACRO, 1e-6, strain=eps)
+            torch.cuda.synchronize()
+            t_plain = time.perf_counter() - t0
+        tti = {"plain": {"seconds": round(t_plain, 4), "iterations": r2.iterations, "status": r2.status,
+                         "eta": r2.eta, "eta_verify_fp64": r2.eta_verify_fp64,
+                         "C_12_12": float(r2.mean_stress[5]) / 2.0},
+               "learned": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_sample, args.cpu_iters)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "voxel-iter/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{L}^3 sphere-Boolean (r={RECIPE['radius']:g}, f={info.volume_fraction:.4f}, "
+                        f"{info.n_spheres} spheres, seed {RECIPE['seed']}), E 10/1, nu 0.3, eps_12=1, "
+                        "AS + rotated Green operator, f32 fields / f64 reductions",
+            "grid": L,
+            "scheme": "AS",
+            "green": "rotated",
+            "parallelism": "single-gpu",
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "time_to_tol_1e-6": tti,
+        "iteration_bytes_model": step_bytes,
+        "iteration_gbs_model": round(iter_gbs, 1),
+        "passes": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                   for k, v in passes.items()},
+        "library_seconds": round(res.seconds, 4),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

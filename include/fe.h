@@ -86,8 +86,23 @@ typedef struct {
                              iteration count is then a multiple of m            */
   int32_t diverge_window; /* report FE_DIVERGED after this many consecutive
                              increases of eta (default 50; 0 disables)          */
+  int32_t timing;         /* nonzero: time every pass with HIP events on the plan's
+                             stream and report it in fe_result.pass_seconds     */
   void* hip_stream;       /* hipStream_t to run on; NULL = the null stream        */
 } fe_plan_options;
+
+/* Passes of one iteration, indices of fe_result.pass_seconds / pass_launches. */
+enum {
+  FE_PASS_POINTWISE = 0, /* divergence stencil (WP, ROT) or polarization (MS)  */
+  FE_PASS_ZFWD = 1,      /* real-to-complex transform along z                   */
+  FE_PASS_YFWD = 2,      /* complex transform along y                           */
+  FE_PASS_XGREEN = 3,    /* transform along x, Green operator, inverse along x  */
+  FE_PASS_YINV = 4,      /* inverse transform along y                           */
+  FE_PASS_ZINV = 5,      /* complex-to-real transform along z                   */
+  FE_PASS_UPDATE = 6,    /* strain update (gradient stencil or pointwise)       */
+  FE_PASS_ETA = 7,       /* reductions and the extra transforms of eta (MS)     */
+  FE_NUM_PASSES = 8
+};
 
 typedef struct fe_plan fe_plan;
 
@@ -130,6 +145,8 @@ typedef struct {
                               (equals eta for FE_FP64 plans)                           */
   int32_t iterations;      /* n: first k with eta^k <= tol, or the cap                */
   double seconds;          /* wall time of the iteration loop on the device stream    */
+  double pass_seconds[8];  /* with fe_plan_options.timing: summed device time per pass */
+  int32_t pass_launches[8];/* with fe_plan_options.timing: launches per pass          */
 } fe_result;
 
 /*

@@ -426,7 +426,7 @@ def green3_closed_form(ref: Reference, k):
 # ----------------------------------------------------------------------------
 
 _AXES = (-3, -2, -1)
-_WORKERS = os.cpu_count() or 1
+_WORKERS = int(os.environ.get("ORACLE_WORKERS", os.cpu_count() or 1))
 
 
 def forward_dft(f):

@@ -27,6 +27,7 @@ GREEN = {"MS": 0, "WP": 1, "W": 1, "ROT": 2, "R": 2}
 SCHEME = {"DS": 0, "direct": 0, "AS": 1, "accelerated": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 REF_RULE = {"paper": 0, "explicit": 1}
+PASSES = ("pointwise", "zfwd", "yfwd", "xgreen", "yinv", "zinv", "update", "eta")
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 
@@ -50,6 +51,7 @@ class FePlanOptions(C.Structure):
         ("nu0", C.c_double),
         ("check_every", C.c_int32),
         ("diverge_window", C.c_int32),
+        ("timing", C.c_int32),
         ("hip_stream", C.c_void_p),
     ]
 
@@ -69,6 +71,8 @@ class FeResult(C.Structure):
         ("eta_verify_fp64", C.c_double),
         ("iterations", C.c_int32),
         ("seconds", C.c_double),
+        ("pass_seconds", C.c_double * 8),
+        ("pass_launches", C.c_int32 * 8),
     ]
 
 
@@ -152,6 +156,8 @@ class Result:
     mean_stress: np.ndarray
     seconds: float
     eta_history: np.ndarray = field(default=None, repr=False)
+    pass_seconds: dict = field(default=None, repr=False)
+    pass_launches: dict = field(default=None, repr=False)
 
     @property
     def converged(self) -> bool:
@@ -162,7 +168,7 @@ class Plan:
     """A solver plan for one grid, Green operator and scheme (fe_plan_create)."""
 
     def __init__(self, grid, green="R", scheme="AS", precision="fp32", max_iter=1000, ref_rule="paper",
-                 ds_beta=0.5, E0=0.0, nu0=0.25, check_every=1, diverge_window=50, stream=None):
+                 ds_beta=0.5, E0=0.0, nu0=0.25, check_every=1, diverge_window=50, timing=False, stream=None):
         lib = load_library()
         nx, ny, nz = (grid, grid, grid) if isinstance(grid, int) else tuple(grid)
         self.shape = (nz, ny, nx)
@@ -177,6 +183,7 @@ class Plan:
         opt.nu0 = float(nu0)
         opt.check_every = int(check_every)
         opt.diverge_window = int(diverge_window)
+        opt.timing = 1 if timing else 0
         opt.hip_stream = stream
         h = C.c_void_p()
         s = lib.fe_plan_create(FeGrid(nx, ny, nz), GREEN[green], SCHEME[scheme], C.byref(opt), C.byref(h))
@@ -231,6 +238,8 @@ class Plan:
             raise FeError(s, "fe_solve")
         del keep
         res = Result(s, r.iterations, r.eta, r.eta_verify_fp64, np.array(r.mean_stress[:]), r.seconds)
+        res.pass_seconds = {n: float(r.pass_seconds[i]) for i, n in enumerate(PASSES)}
+        res.pass_launches = {n: int(r.pass_launches[i]) for i, n in enumerate(PASSES)}
         if hist is not None:
             res.eta_history = hist[: min(len(hist), r.iterations + 1)]
         return res

@@ -151,6 +151,41 @@ struct fe_plan {
   Tables<double> t64;
   size_t ws_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t tev[64] = {};  // pass timing pool (pairs)
+};
+
+// Optional per-pass timing: HIP events recorded around each launch on the
+// plan's stream; elapsed times are read back at synchronisation points.
+struct PassTimer {
+  fe_plan* p;
+  bool on;
+  int used = 0;
+  int pass_of[32];
+  double sec[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  PassTimer(fe_plan* plan, bool enabled) : p(plan), on(enabled) {}
+  template <class F>
+  void run(int pass, F&& f) {
+    if (!on) {
+      f();
+      return;
+    }
+    if (used == 32) flush();
+    (void)hipEventRecord(p->tev[2 * used], p->stream);
+    f();
+    (void)hipEventRecord(p->tev[2 * used + 1], p->stream);
+    pass_of[used++] = pass;
+  }
+  void flush() {
+    if (!on || used == 0) return;
+    (void)hipEventSynchronize(p->tev[2 * used - 1]);
+    for (int i = 0; i < used; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p->tev[2 * i], p->tev[2 * i + 1]) == hipSuccess) sec[pass_of[i]] += ms * 1e-3;
+      launches[pass_of[i]]++;
+    }
+    used = 0;
+  }
 };
 
 static size_t elem_size(const fe_plan* p) { return p->opt.precision == FE_FP64 ? 8 : 4; }
@@ -286,6 +321,9 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
   if ((st = upload_tables<double>(p, p->t64)) != FE_OK) return cleanup_fail(st);
   if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
     return cleanup_fail(fail(FE_ERR_DEVICE, "event creation"));
+  if (o.timing)
+    for (int i = 0; i < 64; ++i)
+      if (hipEventCreate(&p->tev[i]) != hipSuccess) return cleanup_fail(fail(FE_ERR_DEVICE, "event creation"));
   *out = p;
   return FE_OK;
 }
@@ -309,6 +347,8 @@ extern "C" void fe_plan_destroy(fe_plan* p) {
   if (p->h_red) (void)hipHostFree(p->h_red);
   if (p->ev0) (void)hipEventDestroy(p->ev0);
   if (p->ev1) (void)hipEventDestroy(p->ev1);
+  for (hipEvent_t e : p->tev)
+    if (e) (void)hipEventDestroy(e);
   delete p;
 }
 
@@ -520,25 +560,29 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
   const int xblk = xeta_blocks<T>(d);
 
   HIP_TRY(hipEventRecord(p->ev0, s));
+  PassTimer tm(p, p->opt.timing != 0);
   fe_status status = FE_NOT_CONVERGED;
   double eta = NAN, prev_eta = INFINITY, mean[6] = {0, 0, 0, 0, 0, 0};
   int rising = 0, k = 0;
   for (k = 0;; ++k) {
     const bool check = (k % every == 0) || k == max_iter;
     if (p->displacement) {
-      Launch<T>::div(eps, phase, coef, R, p->partials, p->div_blocks, d, p->op, s);
-      if (check) launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
+      tm.run(FE_PASS_POINTWISE, [&] { Launch<T>::div(eps, phase, coef, R, p->partials, p->div_blocks, d, p->op, s); });
+      if (check) tm.run(FE_PASS_ETA, [&] { launch_reduce(p->partials, p->div_blocks, 7, p->red, s); });
     } else if (check) {
-      Launch<T>::tau6(eps, phase, coef, R, 1, p->partials, p->div_blocks, d, s);
-      launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
-      Launch<T>::zr2c(R, S, 6, d, tb.tw[2], p->plan_z, s);
-      Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 0, s);
-      Launch<T>::xeta6(S, d, tb.tw[0], p->plan_x, wt, p->partials2, xblk, p->op, s);
-      launch_reduce(p->partials2, xblk, 1, p->red + 8, s);
+      tm.run(FE_PASS_ETA, [&] {
+        Launch<T>::tau6(eps, phase, coef, R, 1, p->partials, p->div_blocks, d, s);
+        launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
+        Launch<T>::zr2c(R, S, 6, d, tb.tw[2], p->plan_z, s);
+        Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 0, s);
+        Launch<T>::xeta6(S, d, tb.tw[0], p->plan_x, wt, p->partials2, xblk, p->op, s);
+        launch_reduce(p->partials2, xblk, 1, p->red + 8, s);
+      });
     }
     if (check) {
       HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
+      tm.flush();
       for (int i = 0; i < 6; ++i) mean[i] = p->h_red[1 + i] / (double)N;
       const double nrm = frob(mean);
       eta = p->displacement ? std::sqrt(p->h_red[0] / (double)N) / nrm : std::sqrt(p->h_red[8]) / ((double)N * nrm);
@@ -563,28 +607,33 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       }
     }
     if (p->displacement) {
-      Launch<T>::zr2c(R, S, 3, d, tb.tw[2], p->plan_z, s);
-      Launch<T>::yfft(S, 3, d, tb.tw[1], p->plan_y, 0, s);
-      Launch<T>::xgreen3(S, d, tb.tw[0], p->plan_x, wt, g, p->op, s);
-      Launch<T>::yfft(S, 3, d, tb.tw[1], p->plan_y, 1, s);
-      Launch<T>::zc2r(S, R, 3, d, tb.tw[2], p->plan_z, s);
-      Launch<T>::grad_update(R, eps, phase, coef, g, d, p->op, accel, s);
+      tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 3, d, tb.tw[2], p->plan_z, s); });
+      tm.run(FE_PASS_YFWD, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], p->plan_y, 0, s); });
+      tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen3(S, d, tb.tw[0], p->plan_x, wt, g, p->op, s); });
+      tm.run(FE_PASS_YINV, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], p->plan_y, 1, s); });
+      tm.run(FE_PASS_ZINV, [&] { Launch<T>::zc2r(S, R, 3, d, tb.tw[2], p->plan_z, s); });
+      tm.run(FE_PASS_UPDATE, [&] { Launch<T>::grad_update(R, eps, phase, coef, g, d, p->op, accel, s); });
     } else {
-      Launch<T>::tau6(eps, phase, coef, R, 0, nullptr, p->div_blocks, d, s);
-      Launch<T>::zr2c(R, S, 6, d, tb.tw[2], p->plan_z, s);
-      Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 0, s);
-      Launch<T>::xgreen6(S, d, tb.tw[0], p->plan_x, wt, g, p->op, s);
-      Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 1, s);
-      Launch<T>::zc2r(S, R, 6, d, tb.tw[2], p->plan_z, s);
-      Launch<T>::update6(R, eps, phase, coef, d, accel, s);
+      tm.run(FE_PASS_POINTWISE, [&] { Launch<T>::tau6(eps, phase, coef, R, 0, nullptr, p->div_blocks, d, s); });
+      tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 6, d, tb.tw[2], p->plan_z, s); });
+      tm.run(FE_PASS_YFWD, [&] { Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 0, s); });
+      tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen6(S, d, tb.tw[0], p->plan_x, wt, g, p->op, s); });
+      tm.run(FE_PASS_YINV, [&] { Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 1, s); });
+      tm.run(FE_PASS_ZINV, [&] { Launch<T>::zc2r(S, R, 6, d, tb.tw[2], p->plan_z, s); });
+      tm.run(FE_PASS_UPDATE, [&] { Launch<T>::update6(R, eps, phase, coef, d, accel, s); });
     }
     HIP_TRY(hipGetLastError());
   }
   HIP_TRY(hipEventRecord(p->ev1, s));
   HIP_TRY(hipEventSynchronize(p->ev1));
+  tm.flush();
   float ms_elapsed = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms_elapsed, p->ev0, p->ev1));
   HIP_TRY(hipGetLastError());
+  for (int i = 0; i < 8; ++i) {
+    out->pass_seconds[i] = tm.sec[i];
+    out->pass_launches[i] = tm.launches[i];
+  }
 
   if (out->stress) Launch<T>::stress(eps, phase, coef, static_cast<T*>(out->stress), N, s);
   double ev = eta;
