@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/fe.h"
+#include "fe_fft.h"
 #include "fe_kernels.h"
 
 using namespace fe;
@@ -40,25 +41,6 @@ static fe_status fail(fe_status s, const char* fmt, ...) {
 // ---------------------------------------------------------------------------
 // host-side tables (float64)
 // ---------------------------------------------------------------------------
-static bool is_2a3b(int n) {
-  if (n <= 0) return false;
-  while (n % 2 == 0) n /= 2;
-  while (n % 3 == 0) n /= 3;
-  return n == 1;
-}
-
-// Radix sequence for the Stockham stages: radix 8 first, then 4, 2, 3.
-static uint32_t radix_plan(int n) {
-  uint32_t plan = 0;
-  int s = 0;
-  auto push = [&](int r) { plan |= (uint32_t)r << (4 * s++); };
-  while (n % 8 == 0) { push(8); n /= 8; }
-  while (n % 4 == 0) { push(4); n /= 4; }
-  while (n % 2 == 0) { push(2); n /= 2; }
-  while (n % 3 == 0) { push(3); n /= 3; }
-  return s <= 8 ? plan : 0;
-}
-
 // cos and sin of 2 pi num / den, exact at multiples of pi/2.  The angle is
 // first reduced to (-pi, pi] so that small angles keep full relative accuracy
 // (sin of an argument near 2 pi loses it).
@@ -133,7 +115,6 @@ struct fe_plan {
   int op;
   bool displacement;  // WP/ROT: 3-component displacement form
   Dims d;
-  uint32_t plan_x, plan_y, plan_z;
   int div_blocks;
   size_t partial_count;
   // workspace
@@ -226,8 +207,6 @@ static fe_status upload_tables(fe_plan* p, Tables<T>& t) {
   return FE_OK;
 }
 
-static std::once_flag g_attr_once[64];
-
 extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme scheme, const fe_plan_options* opt,
                                     fe_plan** out) {
   if (!out) return fail(FE_ERR_INVALID_ARG, "out is NULL");
@@ -257,8 +236,8 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
   const int n[3] = {g.nx, g.ny, g.nz};
   for (int a = 0; a < 3; ++a) {
     if (n[a] <= 0) return fail(FE_ERR_INVALID_ARG, "grid dimension %d is %d", a, n[a]);
-    if (n[a] < 4 || n[a] > 1024 || n[a] % 2 != 0 || !is_2a3b(n[a]))
-      return fail(FE_ERR_UNSUPPORTED, "grid dimension %d = %d: need an even 2^a 3^b in [4, 1024]", a, n[a]);
+    if (!supported_length(n[a]))
+      return fail(FE_ERR_UNSUPPORTED, "grid dimension %d = %d: need 2^a or 3*2^a in [4, 1024]", a, n[a]);
   }
 
   fe_plan* p = new fe_plan();
@@ -274,9 +253,6 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
   p->d.nz = g.nz;
   p->d.H = g.nz / 2 + 1;
   p->d.N = (long long)g.nx * g.ny * g.nz;
-  p->plan_x = radix_plan(g.nx);
-  p->plan_y = radix_plan(g.ny);
-  p->plan_z = radix_plan(g.nz);
   long long db = (p->d.N + kThreads - 1) / kThreads;
   p->div_blocks = (int)(db > kMaxReduceBlocks ? kMaxReduceBlocks : db);
 
@@ -287,14 +263,6 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
     return s;
   };
   if (hipGetDevice(&p->device) != hipSuccess) return cleanup_fail(fail(FE_ERR_DEVICE, "no HIP device"));
-  if (p->device < 64) {
-    int bad = 0;
-    std::call_once(g_attr_once[p->device], [&] {
-      bad |= Launch<float>::set_kernel_attributes();
-      bad |= Launch<double>::set_kernel_attributes();
-    });
-    if (bad) return cleanup_fail(fail(FE_ERR_DEVICE, "hipFuncSetAttribute failed"));
-  }
   const size_t es = elem_size(p);
   const int ncomp = p->displacement ? 3 : 6;
   const long long N = p->d.N;
@@ -473,11 +441,9 @@ static fe_status verify_fp64(fe_plan* p, const TS* eps, const uint8_t* phase, do
   Launch<double>::tau6(e64, phase, p->coef64, r64, 1, p->partials, p->div_blocks, d, s);
   launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
   const Tables<double>& t = p->t64;
-  Launch<double>::zr2c(r64, s64, 6, d, t.tw[2], p->plan_z, s);
-  Launch<double>::yfft(s64, 6, d, t.tw[1], p->plan_y, 0, s);
-  Launch<double>::xeta6(s64, d, t.tw[0], p->plan_x, wave_tables<double>(p), p->partials2, 0, p->op, s);
-  const int nl = std::max(1, TileCap<double>::CAP6 / (6 * d.nx));
-  const int nblk = (d.H * d.ny + nl - 1) / nl;
+  Launch<double>::zr2c(r64, s64, 6, d, t.tw[2], s);
+  Launch<double>::yfft(s64, 6, d, t.tw[1], 0, s);
+  const int nblk = Launch<double>::xeta6(s64, d, t.tw[0], wave_tables<double>(p), p->partials2, p->op, s);
   launch_reduce(p->partials2, nblk, 1, p->red + 8, s);
   HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -488,12 +454,6 @@ static fe_status verify_fp64(fe_plan* p, const TS* eps, const uint8_t* phase, do
   for (int i = 0; i < 6; ++i) ms[i] = p->h_red[1 + i] / (double)d.N;
   *eta_out = std::sqrt(p->h_red[8]) / ((double)d.N * frob(ms));
   return FE_OK;
-}
-
-template <typename T>
-static int xeta_blocks(const Dims& d) {
-  const int nl = std::max(1, TileCap<T>::CAP6 / (6 * d.nx));
-  return (d.H * d.ny + nl - 1) / nl;
 }
 
 template <typename T>
@@ -557,7 +517,6 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
   const int accel = p->scheme == FE_ACCELERATED;
   const int max_iter = p->opt.max_iter;
   const int every = p->opt.check_every;
-  const int xblk = xeta_blocks<T>(d);
 
   HIP_TRY(hipEventRecord(p->ev0, s));
   PassTimer tm(p, p->opt.timing != 0);
@@ -573,9 +532,9 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       tm.run(FE_PASS_ETA, [&] {
         Launch<T>::tau6(eps, phase, coef, R, 1, p->partials, p->div_blocks, d, s);
         launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
-        Launch<T>::zr2c(R, S, 6, d, tb.tw[2], p->plan_z, s);
-        Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 0, s);
-        Launch<T>::xeta6(S, d, tb.tw[0], p->plan_x, wt, p->partials2, xblk, p->op, s);
+        Launch<T>::zr2c(R, S, 6, d, tb.tw[2], s);
+        Launch<T>::yfft(S, 6, d, tb.tw[1], 0, s);
+        const int xblk = Launch<T>::xeta6(S, d, tb.tw[0], wt, p->partials2, p->op, s);
         launch_reduce(p->partials2, xblk, 1, p->red + 8, s);
       });
     }
@@ -607,19 +566,19 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       }
     }
     if (p->displacement) {
-      tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 3, d, tb.tw[2], p->plan_z, s); });
-      tm.run(FE_PASS_YFWD, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], p->plan_y, 0, s); });
-      tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen3(S, d, tb.tw[0], p->plan_x, wt, g, p->op, s); });
-      tm.run(FE_PASS_YINV, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], p->plan_y, 1, s); });
-      tm.run(FE_PASS_ZINV, [&] { Launch<T>::zc2r(S, R, 3, d, tb.tw[2], p->plan_z, s); });
+      tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 3, d, tb.tw[2], s); });
+      tm.run(FE_PASS_YFWD, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], 0, s); });
+      tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen3(S, d, tb.tw[0], wt, g, p->op, s); });
+      tm.run(FE_PASS_YINV, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], 1, s); });
+      tm.run(FE_PASS_ZINV, [&] { Launch<T>::zc2r(S, R, 3, d, tb.tw[2], s); });
       tm.run(FE_PASS_UPDATE, [&] { Launch<T>::grad_update(R, eps, phase, coef, g, d, p->op, accel, s); });
     } else {
       tm.run(FE_PASS_POINTWISE, [&] { Launch<T>::tau6(eps, phase, coef, R, 0, nullptr, p->div_blocks, d, s); });
-      tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 6, d, tb.tw[2], p->plan_z, s); });
-      tm.run(FE_PASS_YFWD, [&] { Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 0, s); });
-      tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen6(S, d, tb.tw[0], p->plan_x, wt, g, p->op, s); });
-      tm.run(FE_PASS_YINV, [&] { Launch<T>::yfft(S, 6, d, tb.tw[1], p->plan_y, 1, s); });
-      tm.run(FE_PASS_ZINV, [&] { Launch<T>::zc2r(S, R, 6, d, tb.tw[2], p->plan_z, s); });
+      tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 6, d, tb.tw[2], s); });
+      tm.run(FE_PASS_YFWD, [&] { Launch<T>::yfft(S, 6, d, tb.tw[1], 0, s); });
+      tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen6(S, d, tb.tw[0], wt, g, p->op, s); });
+      tm.run(FE_PASS_YINV, [&] { Launch<T>::yfft(S, 6, d, tb.tw[1], 1, s); });
+      tm.run(FE_PASS_ZINV, [&] { Launch<T>::zc2r(S, R, 6, d, tb.tw[2], s); });
       tm.run(FE_PASS_UPDATE, [&] { Launch<T>::update6(R, eps, phase, coef, d, accel, s); });
     }
     HIP_TRY(hipGetLastError());

@@ -1,6 +1,5 @@
 // Device building blocks for the gfx950 solver: complex arithmetic, small DFT
-// butterflies, one mixed-radix Stockham stage over a tile held in LDS, and
-// deterministic float64 block reductions.
+// butterflies and deterministic float64 block reductions.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -105,80 +104,6 @@ struct Dft<T, 8, INV> {
     v[7] = sub(e[3], o3);
   }
 };
-
-// ---------------------------------------------------------------------------
-// One Stockham autosort stage (Govindaraju et al., SC 2008 formulation) over
-// `ncol` independent length-n sequences in LDS, element (e, col) at
-// lds[e*es + col*cs].  With Ns the product of the radices already applied,
-// butterfly j reads elements j + r n/R, multiplies element r by
-// exp(-+2 pi i r (j mod Ns) / (Ns R)), applies a radix-R DFT and writes
-// element r to (j/Ns) Ns R + (j mod Ns) + r Ns.  Reads complete (barrier)
-// before writes, so the stage runs in place.  Callers barrier before the
-// first stage; every stage ends with a barrier.
-// `tw` holds exp(-2 pi i k / n), k < n (host float64, rounded to T).
-// ---------------------------------------------------------------------------
-template <typename T, int R, int MAXB, bool INV>
-__device__ __forceinline__ void stockham_stage(cpx<T>* lds, int n, int ncol, int es, int cs, int Ns,
-                                               const cpx<T>* __restrict__ tw, int tid, int nthr) {
-  const int nq = n / R;
-  const int nbf = ncol * nq;
-  const int tstep = n / (Ns * R);
-  cpx<T> v[MAXB][R];
-  int dst[MAXB];
-#pragma unroll
-  for (int i = 0; i < MAXB; ++i) {
-    const int b = tid + i * nthr;
-    dst[i] = -1;
-    if (b < nbf) {
-      const int col = b % ncol;
-      const int j = b / ncol;
-      const int k = j % Ns;
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = lds[(j + r * nq) * es + col * cs];
-      const int step = k * tstep;
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cpx<T> w = tw[r * step];
-        if (INV) w.im = -w.im;
-        v[i][r] = mul(v[i][r], w);
-      }
-      Dft<T, R, INV>::run(v[i]);
-      dst[i] = ((j / Ns) * Ns * R + k) * es + col * cs;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < MAXB; ++i) {
-    if (dst[i] >= 0) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) lds[dst[i] + r * Ns * es] = v[i][r];
-    }
-  }
-  __syncthreads();
-}
-
-// Radix plan of a length: up to 8 stages, 4 bits each, radices in {2,3,4,8}.
-__host__ __device__ inline int radix_at(uint32_t plan, int s) { return (plan >> (4 * s)) & 0xF; }
-
-// Full in-place FFT of a tile in LDS.  NTHR threads; CAP = max ncol*n.
-template <typename T, bool INV, int NTHR, int CAP>
-__device__ __forceinline__ void fft_tile(cpx<T>* lds, int n, int ncol, int es, int cs,
-                                         const cpx<T>* __restrict__ tw, uint32_t plan) {
-  const int tid = threadIdx.x;
-  int Ns = 1;
-#pragma unroll 1
-  for (int s = 0; s < 8; ++s) {
-    const int R = radix_at(plan, s);
-    if (R == 0) break;
-    switch (R) {
-      case 8: stockham_stage<T, 8, (CAP + 8 * NTHR - 1) / (8 * NTHR), INV>(lds, n, ncol, es, cs, Ns, tw, tid, NTHR); break;
-      case 4: stockham_stage<T, 4, (CAP + 4 * NTHR - 1) / (4 * NTHR), INV>(lds, n, ncol, es, cs, Ns, tw, tid, NTHR); break;
-      case 3: stockham_stage<T, 3, (CAP + 3 * NTHR - 1) / (3 * NTHR), INV>(lds, n, ncol, es, cs, Ns, tw, tid, NTHR); break;
-      default: stockham_stage<T, 2, (CAP + 2 * NTHR - 1) / (2 * NTHR), INV>(lds, n, ncol, es, cs, Ns, tw, tid, NTHR); break;
-    }
-    Ns *= R;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Deterministic float64 reductions: wavefront shuffle tree, then a fixed

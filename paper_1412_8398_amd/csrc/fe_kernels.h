@@ -50,32 +50,32 @@ struct Launch {
   static void convert_to(T* dst, const void* src, int src_is_double, long long n, hipStream_t s);
   static void check_phase(const uint8_t* phase, long long N, int n_phases, int* flag, hipStream_t s);
 
-  // Pipeline for the WP and ROT operators (displacement form).
+  // Displacement form (WP and ROT operators).
   static void div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, double* partials,
                   int nblocks, Dims d, int op, hipStream_t s);
   static void grad_update(const T* U, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef,
                           GreenConst<T> g, Dims d, int op, int accelerated, hipStream_t s);
-  static void xgreen3(cpx<T>* S, Dims d, const cpx<T>* twx, uint32_t planx, WaveTables<T> wt,
-                      GreenConst<T> g, int op, hipStream_t s);
+  static void xgreen3(cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> wt, GreenConst<T> g, int op,
+                      hipStream_t s);
 
-  // Pipeline for every operator (6-component form).
+  // Six-component form (every operator).
   static void tau6(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* out, int write_sigma,
                    double* partials, int nblocks, Dims d, hipStream_t s);
-  static void xgreen6(cpx<T>* S, Dims d, const cpx<T>* twx, uint32_t planx, WaveTables<T> wt,
-                      GreenConst<T> g, int op, hipStream_t s);
-  static void xeta6(const cpx<T>* S, Dims d, const cpx<T>* twx, uint32_t planx, WaveTables<T> wt,
-                    double* partials, int nblocks, int op, hipStream_t s);
+  static void xgreen6(cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> wt, GreenConst<T> g, int op,
+                      hipStream_t s);
+  // Returns the number of partial sums written.
+  static int xeta6(const cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> wt, double* partials, int op,
+                   hipStream_t s);
   static void update6(const T* e, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, Dims d,
                       int accelerated, hipStream_t s);
 
   // Strided FFT passes.
-  static void zr2c(const T* R, cpx<T>* S, int ncomp, Dims d, const cpx<T>* twz, uint32_t planz, hipStream_t s);
-  static void zc2r(const cpx<T>* S, T* R, int ncomp, Dims d, const cpx<T>* twz, uint32_t planz, hipStream_t s);
-  static void yfft(cpx<T>* S, int ncomp, Dims d, const cpx<T>* twy, uint32_t plany, int inverse, hipStream_t s);
+  static void zr2c(const T* R, cpx<T>* S, int ncomp, Dims d, const cpx<T>* twz, hipStream_t s);
+  static void zc2r(const cpx<T>* S, T* R, int ncomp, Dims d, const cpx<T>* twz, hipStream_t s);
+  static void yfft(cpx<T>* S, int ncomp, Dims d, const cpx<T>* twy, int inverse, hipStream_t s);
 
   static void stress(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* sigma, long long N,
                      hipStream_t s);
-  static int set_kernel_attributes();
 };
 
 // float64 verification of eta from a strain of storage type TS (ROT, WP).
@@ -84,20 +84,6 @@ void launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<doub
                        int nblocks, Dims d, int op, hipStream_t s);
 
 void launch_reduce(const double* partials, int nblocks, int nv, double* out, hipStream_t s);
-
-// Tile sizes (elements of the LDS tile) per real type.
-template <typename T>
-struct TileCap;
-template <>
-struct TileCap<float> {
-  static constexpr int CAP = 8192;   // 64 KiB of complex float
-  static constexpr int CAP6 = 8192;
-};
-template <>
-struct TileCap<double> {
-  static constexpr int CAP = 4096;   // 64 KiB of complex double
-  static constexpr int CAP6 = 6144;  // 96 KiB: six components of a 1024-long line
-};
 
 constexpr int kThreads = 256;
 constexpr int kMaxReduceBlocks = 4096;

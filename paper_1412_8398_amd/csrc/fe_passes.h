@@ -1,0 +1,294 @@
+// FFT pass kernels (compile-time lengths) and their launchers.
+//
+// Spectrum layout: half spectra along z, [comp][mz][y][x] complex, mz in
+// [0, nz/2].  Real planes: [comp][z][y][x].
+#pragma once
+
+#include <type_traits>
+
+#include "fe_fft.h"
+#include "fe_green.h"
+
+namespace fe {
+
+template <typename T>
+constexpr int lds_budget() {  // complex elements per workgroup tile
+  return (64 * 1024) / (int)sizeof(cpx<T>);
+}
+constexpr int imin(int a, int b) { return a < b ? a : b; }
+constexpr int imax(int a, int b) { return a > b ? a : b; }
+
+// Strided passes: TX adjacent x-columns per workgroup, P = N/E threads per
+// column, E elements per thread; 256 threads unless the LDS tile caps TX.
+template <typename T, int N>
+struct StridedCfg {
+  static constexpr int E = e_strided(N);
+  static constexpr int P = N / E;
+  static constexpr int TX = imax(1, imin(256 / P, lds_budget<T>() / N));
+  static constexpr int NT = TX * P;
+};
+
+// x passes: LPB lines per workgroup, P = N/E threads per line.
+template <typename T, int N, int NC>
+struct LineCfg {
+  static constexpr int E = NC == 3 ? e_x3(N) : e_x6(N);
+  static constexpr int P = N / E;
+  static constexpr int LPB = imax(1, 256 / P);
+  static constexpr int NT = LPB * P;
+  static constexpr int LINE = N + N / 16;  // LDS line pitch: one pad per 16 elements
+};
+
+__device__ __forceinline__ int pad16(int pos) { return pos + (pos >> 4); }
+
+template <typename T>
+struct alignas(4 * sizeof(T)) cpx2 {
+  cpx<T> a, b;
+};
+
+// ---------------------------------------------------------------------------
+// y: complex transform of the half spectrum along y, in place
+// ---------------------------------------------------------------------------
+template <typename T, int N, bool INV>
+__global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_ypass(cpx<T>* __restrict__ S, Dims d,
+                                                                const cpx<T>* __restrict__ tw) {
+  using C = StridedCfg<T, N>;
+  __shared__ cpx<T> lds[N * C::TX];
+  const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
+  const int ntx = (d.nx + C::TX - 1) / C::TX;
+  const int xt = blockIdx.x % ntx;
+  const int rest = blockIdx.x / ntx;
+  const int mz = rest % d.H;
+  const int c = rest / d.H;
+  const int x = xt * C::TX + col;
+  const bool ok = x < d.nx;
+  cpx<T>* base = S + ((long long)c * d.H + mz) * (long long)N * d.nx + (ok ? x : 0);
+  cpx<T> v[1][C::E];
+#pragma unroll
+  for (int m = 0; m < C::E; ++m) v[0][m] = ok ? base[(long long)(t + m * C::P) * d.nx] : mk(T(0), T(0));
+  fft_regs<T, N, C::E, 1, INV>(v, t, lds, [col](int, int pos) { return pos * C::TX + col; }, tw);
+  if (ok) {
+#pragma unroll
+    for (int m = 0; m < C::E; ++m) base[(long long)(t + m * C::P) * d.nx] = v[0][m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z: real-to-complex.  Two adjacent real x-columns are one complex column
+// z = a + i b; after the transform A(m) = (Z(m) + conj Z(-m))/2 and
+// B(m) = (Z(m) - conj Z(-m))/(2i) for m in [0, nz/2].
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __restrict__ R, cpx<T>* __restrict__ S,
+                                                               Dims d, const cpx<T>* __restrict__ tw) {
+  using C = StridedCfg<T, N>;
+  __shared__ cpx<T> lds[N * C::TX];
+  const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
+  const int npair = d.nx / 2;
+  const int ntx = (npair + C::TX - 1) / C::TX;
+  const int xt = blockIdx.x % ntx;
+  const int rest = blockIdx.x / ntx;
+  const int y = rest % d.ny;
+  const int c = rest / d.ny;
+  const int pp = xt * C::TX + col;
+  const bool ok = pp < npair;
+  const long long plane = (long long)d.ny * d.nx;
+  const T* src = R + (long long)c * d.N + (long long)y * d.nx + 2 * (ok ? pp : 0);
+  cpx<T> v[1][C::E];
+#pragma unroll
+  for (int m = 0; m < C::E; ++m)
+    v[0][m] = ok ? *reinterpret_cast<const cpx<T>*>(src + (long long)(t + m * C::P) * plane) : mk(T(0), T(0));
+  fft_regs<T, N, C::E, 1, false>(v, t, lds, [col](int, int pos) { return pos * C::TX + col; }, tw);
+#pragma unroll
+  for (int m = 0; m < C::E; ++m) lds[(t + m * C::P) * C::TX + col] = v[0][m];
+  __syncthreads();
+  cpx2<T>* dst = reinterpret_cast<cpx2<T>*>(S + (long long)c * d.H * plane + (long long)y * d.nx + 2 * (ok ? pp : 0));
+  for (int mz = t; mz < d.H; mz += C::P) {
+    const cpx<T> Z = lds[mz * C::TX + col];
+    const cpx<T> Zm = conj(lds[((N - mz) % N) * C::TX + col]);
+    const cpx<T> Dd = sub(Z, Zm);
+    cpx2<T> o;
+    o.a = scale(add(Z, Zm), T(0.5));
+    o.b = mk(T(0.5) * Dd.im, T(-0.5) * Dd.re);
+    if (ok) *reinterpret_cast<cpx2<T>*>(reinterpret_cast<cpx<T>*>(dst) + (long long)mz * plane) = o;
+  }
+}
+
+// z: complex-to-real (unnormalised inverse): Z(m) = A(m) + i B(m),
+// Z(nz-m) = conj A(m) + i conj B(m); the inverse transform of Z is a + i b.
+template <typename T, int N>
+__global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* __restrict__ S, T* __restrict__ R,
+                                                               Dims d, const cpx<T>* __restrict__ tw) {
+  using C = StridedCfg<T, N>;
+  __shared__ cpx<T> lds[N * C::TX];
+  const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
+  const int npair = d.nx / 2;
+  const int ntx = (npair + C::TX - 1) / C::TX;
+  const int xt = blockIdx.x % ntx;
+  const int rest = blockIdx.x / ntx;
+  const int y = rest % d.ny;
+  const int c = rest / d.ny;
+  const int pp = xt * C::TX + col;
+  const bool ok = pp < npair;
+  const long long plane = (long long)d.ny * d.nx;
+  const cpx<T>* src = S + (long long)c * d.H * plane + (long long)y * d.nx + 2 * (ok ? pp : 0);
+  for (int mz = t; mz < d.H; mz += C::P) {
+    cpx2<T> ab;
+    if (ok) {
+      ab = *reinterpret_cast<const cpx2<T>*>(src + (long long)mz * plane);
+    } else {
+      ab.a = mk(T(0), T(0));
+      ab.b = mk(T(0), T(0));
+    }
+    const cpx<T> A = ab.a, B = ab.b;
+    lds[mz * C::TX + col] = mk(A.re - B.im, A.im + B.re);
+    if (mz > 0 && 2 * mz < N) lds[(N - mz) * C::TX + col] = mk(A.re + B.im, B.re - A.im);
+  }
+  __syncthreads();
+  cpx<T> v[1][C::E];
+#pragma unroll
+  for (int m = 0; m < C::E; ++m) v[0][m] = lds[(t + m * C::P) * C::TX + col];
+  __syncthreads();
+  fft_regs<T, N, C::E, 1, true>(v, t, lds, [col](int, int pos) { return pos * C::TX + col; }, tw);
+  if (ok) {
+    T* dst = R + (long long)c * d.N + (long long)y * d.nx + 2 * pp;
+#pragma unroll
+    for (int m = 0; m < C::E; ++m) *reinterpret_cast<cpx<T>*>(dst + (long long)(t + m * C::P) * plane) = v[0][m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x: forward transform of each contiguous x-line, Green operator per
+// frequency in registers, inverse transform; components take turns in LDS.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int OP>
+__global__ __launch_bounds__((LineCfg<T, N, 3>::NT)) void k_xgreen3(cpx<T>* __restrict__ S, Dims d,
+                                                                  const cpx<T>* __restrict__ tw, WaveTables<T> wt,
+                                                                  GreenConst<T> g) {
+  using C = LineCfg<T, N, 3>;
+  __shared__ cpx<T> lds[C::LPB * C::LINE];
+  const int t = threadIdx.x % C::P, l = threadIdx.x / C::P;
+  const int nlines = d.H * d.ny;
+  const int line = blockIdx.x * C::LPB + l;
+  const bool ok = line < nlines;
+  const long long cs = (long long)nlines * N;
+  cpx<T>* base = S + (long long)(ok ? line : 0) * N + t;
+  cpx<T> v[3][C::E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int m = 0; m < C::E; ++m) v[c][m] = ok ? base[c * cs + m * C::P] : mk(T(0), T(0));
+  const auto at = [l](int, int pos) { return l * C::LINE + pad16(pos); };
+  fft_regs<T, N, C::E, 3, false, true>(v, t, lds, at, tw);
+  const int mz = (ok ? line : 0) / d.ny, my = (ok ? line : 0) % d.ny;
+#pragma unroll
+  for (int m = 0; m < C::E; ++m) {
+    cpx<T> b[3] = {v[0][m], v[1][m], v[2][m]};
+    green_disp<T, OP>(b, wt, t + m * C::P, my, mz, g);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c][m] = b[c];
+  }
+  fft_regs<T, N, C::E, 3, true, true>(v, t, lds, at, tw);
+  if (ok) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int m = 0; m < C::E; ++m) base[c * cs + m * C::P] = v[c][m];
+  }
+}
+
+template <typename T, int N, int OP>
+__global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xgreen6(cpx<T>* __restrict__ S, Dims d,
+                                                                  const cpx<T>* __restrict__ tw, WaveTables<T> wt,
+                                                                  GreenConst<T> g) {
+  using C = LineCfg<T, N, 6>;
+  __shared__ cpx<T> lds[C::LPB * C::LINE];
+  const int t = threadIdx.x % C::P, l = threadIdx.x / C::P;
+  const int nlines = d.H * d.ny;
+  const int line = blockIdx.x * C::LPB + l;
+  const bool ok = line < nlines;
+  const long long cs = (long long)nlines * N;
+  cpx<T>* base = S + (long long)(ok ? line : 0) * N + t;
+  cpx<T> v[6][C::E];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int m = 0; m < C::E; ++m) v[c][m] = ok ? base[c * cs + m * C::P] : mk(T(0), T(0));
+  const auto at = [l](int, int pos) { return l * C::LINE + pad16(pos); };
+  fft_regs<T, N, C::E, 6, false, true>(v, t, lds, at, tw);
+  const int mz = (ok ? line : 0) / d.ny, my = (ok ? line : 0) % d.ny;
+#pragma unroll
+  for (int m = 0; m < C::E; ++m) {
+    cpx<T> tv[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tv[c] = v[c][m];
+    green_six<T, OP>(tv, wt, t + m * C::P, my, mz, g);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c][m] = tv[c];
+  }
+  fft_regs<T, N, C::E, 6, true, true>(v, t, lds, at, tw);
+  if (ok) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+#pragma unroll
+      for (int m = 0; m < C::E; ++m) base[c * cs + m * C::P] = v[c][m];
+  }
+}
+
+template <typename T, int N, int OP>
+__global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xeta6(const cpx<T>* __restrict__ S, Dims d,
+                                                                const cpx<T>* __restrict__ tw, WaveTables<T> wt,
+                                                                double* __restrict__ partials) {
+  using C = LineCfg<T, N, 6>;
+  __shared__ cpx<T> lds[C::LPB * C::LINE];
+  __shared__ double red[16];
+  const int t = threadIdx.x % C::P, l = threadIdx.x / C::P;
+  const int nlines = d.H * d.ny;
+  const int line = blockIdx.x * C::LPB + l;
+  const bool ok = line < nlines;
+  const long long cs = (long long)nlines * N;
+  const cpx<T>* base = S + (long long)(ok ? line : 0) * N + t;
+  cpx<T> v[6][C::E];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int m = 0; m < C::E; ++m) v[c][m] = ok ? base[c * cs + m * C::P] : mk(T(0), T(0));
+  const auto at = [l](int, int pos) { return l * C::LINE + pad16(pos); };
+  fft_regs<T, N, C::E, 6, false, true>(v, t, lds, at, tw);
+  const int mz = (ok ? line : 0) / d.ny, my = (ok ? line : 0) % d.ny;
+  double acc[1] = {0.0};
+  if (ok) {
+#pragma unroll
+    for (int m = 0; m < C::E; ++m) {
+      cpx<T> sv[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sv[c] = v[c][m];
+      acc[0] += eta_six<T, OP>(sv, wt, t + m * C::P, my, mz, d);
+    }
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+}
+
+// ---------------------------------------------------------------------------
+// length dispatch
+// ---------------------------------------------------------------------------
+template <class F>
+static bool dispatch_length(int n, F&& f) {
+  switch (n) {
+#define FE_CASE(NN)                                \
+  case NN:                                         \
+    f(std::integral_constant<int, NN>());          \
+    return true;
+    FE_FOR_EACH_LENGTH(FE_CASE)
+#undef FE_CASE
+  }
+  return false;
+}
+
+template <typename T, int N>
+inline int x_blocks(const Dims& d, int nc) {
+  const int lpb = nc == 3 ? LineCfg<T, N, 3>::LPB : LineCfg<T, N, 6>::LPB;
+  return (d.H * d.ny + lpb - 1) / lpb;
+}
+
+}  // namespace fe

@@ -1,0 +1,458 @@
+// gfx950 kernels of the Lippmann-Schwinger FFT iteration (Willot, arXiv
+// 1412.8398).  Equation numbers refer to the paper.
+//
+// Layouts: real fields are SoA planes [comp][z][y][x] of N = nx*ny*nz values;
+// spectra are half spectra along z: [comp][mz][y][x] complex, mz in [0, nz/2].
+// Tensor components use Voigt order (11, 22, 33, 23, 13, 12).
+#include "fe_green.h"
+
+namespace fe {
+
+// --------------------------------------------------------------------------
+// helpers
+// --------------------------------------------------------------------------
+
+
+template <typename T>
+__device__ __forceinline__ void load6(const T* __restrict__ f, long long N, long long idx, T (&v)[6]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) v[c] = f[c * N + idx];
+}
+
+// sigma = lam tr(eps) I + 2 mu eps  (eq. (2)); same form gives tau with (dlam, dmu).
+template <typename T>
+__device__ __forceinline__ void iso_apply(T lam, T mu, const T (&e)[6], T (&s)[6]) {
+  const T tr = e[0] + e[1] + e[2];
+  const T l = lam * tr;
+  const T m2 = T(2) * mu;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) s[c] = l + m2 * e[c];
+#pragma unroll
+  for (int c = 3; c < 6; ++c) s[c] = m2 * e[c];
+}
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// --------------------------------------------------------------------------
+// initialisation, checks, conversions
+// --------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_fill_macro(T* __restrict__ eps, long long N, T m0, T m1, T m2, T m3, T m4, T m5) {
+  const T m[6] = {m0, m1, m2, m3, m4, m5};
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) eps[c * N + i] = m[c];
+  }
+}
+
+template <typename T, typename S>
+__global__ void k_convert(T* __restrict__ dst, const S* __restrict__ src, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = T(src[i]);
+}
+
+__global__ void k_check_phase(const uint8_t* __restrict__ phase, long long N, int n_phases, int* flag) {
+  int bad = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x)
+    bad |= (phase[i] >= n_phases);
+  if (bad) atomicOr(flag, 1);
+}
+
+static int grid_for(long long n, int cap = 8192) {
+  long long b = (n + kThreads - 1) / kThreads;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// --------------------------------------------------------------------------
+// divergence stencils (displacement form, WP and ROT)
+//
+// ROT: at corner c (position c - 1/2, i.e. the lower corner of voxel c) the
+// divergence of a voxel field s is
+//   D_j(c) = 1/4 sum_i [ sum_{a in {0,1}^3, a_i=1} s_ij(c-a) - sum_{a_i=0} s_ij(c-a) ],
+// the corner stencil of eq. (38) (up to the factor -1/4); its Fourier symbol
+// is conj(k^R) of eq. (36).
+// WP: backward differences at voxel x, D_j = sum_i s_ij(x) - s_ij(x - e_i)
+// (eq. (23)), symbol -conj(k^W).
+// The kernel writes D[tau] and accumulates |D[sigma]|^2 and sum sigma in
+// float64 (eq. (43) and eq. (5)).
+// --------------------------------------------------------------------------
+
+template <typename TS, typename TC, int OP, bool WRITE_D>
+__global__ __launch_bounds__(256) void k_div(const TS* __restrict__ eps, const uint8_t* __restrict__ phase,
+                                             const PhaseCoef<TC>* __restrict__ coef, TS* __restrict__ D,
+                                             double* __restrict__ partials, Dims d) {
+  __shared__ double red[7 * 16];
+  const long long N = d.N;
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(c % nx);
+    const int y = (int)((c / nx) % ny);
+    const int z = (int)(c / ((long long)nx * ny));
+    TC Dt[3] = {0, 0, 0}, Ds[3] = {0, 0, 0};
+    if (OP == OP_ROT) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+        const long long v = ((long long)wrap(z - az, nz) * ny + wrap(y - ay, ny)) * nx + wrap(x - ax, nx);
+        TC e[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) e[k] = TC(eps[k * N + v]);
+        const PhaseCoef<TC> pc = coef[phase[v]];
+        TC t[6], s[6];
+        iso_apply(pc.dlam, pc.dmu, e, t);
+        iso_apply(pc.lam, pc.mu, e, s);
+        const int sg[3] = {ax ? 1 : -1, ay ? 1 : -1, az ? 1 : -1};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            const int q = voigt_of(i, j);
+            Dt[j] += sg[i] * t[q];
+            Ds[j] += sg[i] * s[q];
+          }
+        }
+        if (a == 0) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) acc[1 + k] += double(s[k]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        Dt[j] *= TC(0.25);
+        Ds[j] *= TC(0.25);
+      }
+    } else {  // OP_WP
+      {
+        TC e[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) e[k] = TC(eps[k * N + c]);
+        const PhaseCoef<TC> pc = coef[phase[c]];
+        TC t[6], s[6];
+        iso_apply(pc.dlam, pc.dmu, e, t);
+        iso_apply(pc.lam, pc.mu, e, s);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            Dt[j] += t[voigt_of(i, j)];
+            Ds[j] += s[voigt_of(i, j)];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[1 + k] += double(s[k]);
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int xm = i == 0 ? wrap(x - 1, nx) : x;
+        const int ym = i == 1 ? wrap(y - 1, ny) : y;
+        const int zm = i == 2 ? wrap(z - 1, nz) : z;
+        const long long v = ((long long)zm * ny + ym) * nx + xm;
+        TC e[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) e[k] = TC(eps[k * N + v]);
+        const PhaseCoef<TC> pc = coef[phase[v]];
+        TC t[6], s[6];
+        iso_apply(pc.dlam, pc.dmu, e, t);
+        iso_apply(pc.lam, pc.mu, e, s);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          Dt[j] -= t[voigt_of(i, j)];
+          Ds[j] -= s[voigt_of(i, j)];
+        }
+      }
+    }
+    if (WRITE_D) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) D[j * N + c] = TS(Dt[j]);
+    }
+    acc[0] += double(Ds[0]) * double(Ds[0]) + double(Ds[1]) * double(Ds[1]) + double(Ds[2]) * double(Ds[2]);
+  }
+  block_sum<7>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) partials[blockIdx.x * 7 + i] = acc[i];
+  }
+}
+
+// --------------------------------------------------------------------------
+// strain update from the displacement U (WP, ROT)
+// ROT: grad at voxel v from its corners v + a: d_i U_j = 1/4 sum_a s_i(a) U_j(v+a),
+// s_i(a) = +1 if a_i = 1 else -1 (eq. (37)), symbol k^R.
+// WP: forward differences d_i U_j = U_j(v + e_i) - U_j(v) (eq. (23)), symbol k^W.
+// e = eps_bar + sym grad U;  DS (eq. (9)): eps <- e;
+// AS (eq. (16)): eps <- eps + 2 kappa0/(kappa+kappa0) sph(e - eps) + 2 mu0/(mu+mu0) dev(e - eps).
+// --------------------------------------------------------------------------
+
+template <typename T, int OP, bool AS>
+__global__ __launch_bounds__(256) void k_grad_update(const T* __restrict__ U, T* __restrict__ eps,
+                                                     const uint8_t* __restrict__ phase,
+                                                     const PhaseCoef<T>* __restrict__ coef, GreenConst<T> g,
+                                                     Dims d) {
+  const long long N = d.N;
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(v % nx);
+    const int y = (int)((v / nx) % ny);
+    const int z = (int)(v / ((long long)nx * ny));
+    T gr[3][3];  // gr[i][j] = d_i U_j
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) gr[i][j] = T(0);
+    if (OP == OP_ROT) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+        const long long c = ((long long)wrap(z + az, nz) * ny + wrap(y + ay, ny)) * nx + wrap(x + ax, nx);
+        const T u[3] = {U[c], U[N + c], U[2 * N + c]};
+        const T sg[3] = {ax ? T(1) : T(-1), ay ? T(1) : T(-1), az ? T(1) : T(-1)};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) gr[i][j] += sg[i] * u[j];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gr[i][j] *= T(0.25);
+    } else {
+      const T u0[3] = {U[v], U[N + v], U[2 * N + v]};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int xp = i == 0 ? wrap(x + 1, nx) : x;
+        const int yp = i == 1 ? wrap(y + 1, ny) : y;
+        const int zp = i == 2 ? wrap(z + 1, nz) : z;
+        const long long c = ((long long)zp * ny + yp) * nx + xp;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gr[i][j] = U[j * N + c] - u0[j];
+      }
+    }
+    T e[6];
+    e[0] = g.macro[0] + gr[0][0];
+    e[1] = g.macro[1] + gr[1][1];
+    e[2] = g.macro[2] + gr[2][2];
+    e[3] = g.macro[3] + T(0.5) * (gr[1][2] + gr[2][1]);
+    e[4] = g.macro[4] + T(0.5) * (gr[0][2] + gr[2][0]);
+    e[5] = g.macro[5] + T(0.5) * (gr[0][1] + gr[1][0]);
+    if (AS) {
+      const PhaseCoef<T> pc = coef[phase[v]];
+      T cur[6], dd[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        cur[k] = eps[k * N + v];
+        dd[k] = e[k] - cur[k];
+      }
+      const T sph = (dd[0] + dd[1] + dd[2]) * T(1.0 / 3.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) eps[k * N + v] = cur[k] + pc.ak * sph + pc.am * (dd[k] - sph);
+#pragma unroll
+      for (int k = 3; k < 6; ++k) eps[k * N + v] = cur[k] + pc.am * dd[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) eps[k * N + v] = e[k];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// pointwise polarization / stress (6-component form) and update
+// --------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tau6(const T* __restrict__ eps, const uint8_t* __restrict__ phase,
+                                              const PhaseCoef<T>* __restrict__ coef, T* __restrict__ out,
+                                              int write_sigma, double* __restrict__ partials, long long N) {
+  __shared__ double red[7 * 16];
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+    T e[6];
+    load6(eps, N, v, e);
+    const PhaseCoef<T> pc = coef[phase[v]];
+    T s[6], t[6];
+    iso_apply(pc.lam, pc.mu, e, s);
+    iso_apply(pc.dlam, pc.dmu, e, t);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      out[k * N + v] = write_sigma ? s[k] : t[k];
+      acc[1 + k] += double(s[k]);
+    }
+  }
+  if (partials) {
+    block_sum<7>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) partials[blockIdx.x * 7 + i] = acc[i];
+    }
+  }
+}
+
+template <typename T, bool AS>
+__global__ __launch_bounds__(256) void k_update6(const T* __restrict__ e, T* __restrict__ eps,
+                                                 const uint8_t* __restrict__ phase,
+                                                 const PhaseCoef<T>* __restrict__ coef, long long N) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+    if (AS) {
+      const PhaseCoef<T> pc = coef[phase[v]];
+      T cur[6], dd[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        cur[k] = eps[k * N + v];
+        dd[k] = e[k * N + v] - cur[k];
+      }
+      const T sph = (dd[0] + dd[1] + dd[2]) * T(1.0 / 3.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) eps[k * N + v] = cur[k] + pc.ak * sph + pc.am * (dd[k] - sph);
+#pragma unroll
+      for (int k = 3; k < 6; ++k) eps[k * N + v] = cur[k] + pc.am * dd[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) eps[k * N + v] = e[k * N + v];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_stress(const T* __restrict__ eps, const uint8_t* __restrict__ phase,
+                                                const PhaseCoef<T>* __restrict__ coef, T* __restrict__ sigma,
+                                                long long N) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+    T e[6], s[6];
+    load6(eps, N, v, e);
+    const PhaseCoef<T> pc = coef[phase[v]];
+    iso_apply(pc.lam, pc.mu, e, s);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sigma[k * N + v] = s[k];
+  }
+}
+
+// --------------------------------------------------------------------------
+// final reduction: fixed-order sum of per-block partials (deterministic)
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int nblocks, int nv,
+                                                double* __restrict__ out) {
+  __shared__ double red[8 * 16];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+    for (int i = 0; i < nv && i < 8; ++i) acc[i] += partials[(long long)b * nv + i];
+  block_sum<8>(acc, red);
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nv && i < 8; ++i) out[i] = acc[i];
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+
+template <typename T>
+void Launch<T>::fill_macro(T* eps, long long N, const double* m, hipStream_t s) {
+  hipLaunchKernelGGL((k_fill_macro<T>), dim3(grid_for(N)), dim3(kThreads), 0, s, eps, N, T(m[0]), T(m[1]), T(m[2]),
+                     T(m[3]), T(m[4]), T(m[5]));
+}
+
+template <typename T>
+void Launch<T>::convert_to(T* dst, const void* src, int src_is_double, long long n, hipStream_t s) {
+  if (src_is_double)
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(grid_for(n)), dim3(kThreads), 0, s, dst,
+                       static_cast<const double*>(src), n);
+  else
+    hipLaunchKernelGGL((k_convert<T, float>), dim3(grid_for(n)), dim3(kThreads), 0, s, dst,
+                       static_cast<const float*>(src), n);
+}
+
+template <typename T>
+void Launch<T>::check_phase(const uint8_t* phase, long long N, int n_phases, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_phase, dim3(grid_for(N)), dim3(kThreads), 0, s, phase, N, n_phases, flag);
+}
+
+template <typename T>
+void Launch<T>::div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, double* partials,
+                    int nblocks, Dims d, int op, hipStream_t s) {
+  if (op == OP_ROT)
+    hipLaunchKernelGGL((k_div<T, T, OP_ROT, true>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef, D,
+                       partials, d);
+  else
+    hipLaunchKernelGGL((k_div<T, T, OP_WP, true>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef, D,
+                       partials, d);
+}
+
+template <typename TS>
+void launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* partials,
+                       int nblocks, Dims d, int op, hipStream_t s) {
+  if (op == OP_ROT)
+    hipLaunchKernelGGL((k_div<TS, double, OP_ROT, false>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef,
+                       (TS*)nullptr, partials, d);
+  else
+    hipLaunchKernelGGL((k_div<TS, double, OP_WP, false>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef,
+                       (TS*)nullptr, partials, d);
+}
+
+template <typename T>
+void Launch<T>::grad_update(const T* U, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, GreenConst<T> g,
+                            Dims d, int op, int accelerated, hipStream_t s) {
+  const dim3 gr(grid_for(d.N, 1 << 20)), bl(kThreads);
+  if (op == OP_ROT) {
+    if (accelerated)
+      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, true>), gr, bl, 0, s, U, eps, phase, coef, g, d);
+    else
+      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, false>), gr, bl, 0, s, U, eps, phase, coef, g, d);
+  } else {
+    if (accelerated)
+      hipLaunchKernelGGL((k_grad_update<T, OP_WP, true>), gr, bl, 0, s, U, eps, phase, coef, g, d);
+    else
+      hipLaunchKernelGGL((k_grad_update<T, OP_WP, false>), gr, bl, 0, s, U, eps, phase, coef, g, d);
+  }
+}
+
+template <typename T>
+void Launch<T>::tau6(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* out, int write_sigma,
+                     double* partials, int nblocks, Dims d, hipStream_t s) {
+  hipLaunchKernelGGL((k_tau6<T>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef, out, write_sigma, partials,
+                     d.N);
+}
+
+template <typename T>
+void Launch<T>::update6(const T* e, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, Dims d, int accelerated,
+                        hipStream_t s) {
+  if (accelerated)
+    hipLaunchKernelGGL((k_update6<T, true>), dim3(grid_for(d.N, 1 << 20)), dim3(kThreads), 0, s, e, eps, phase, coef,
+                       d.N);
+  else
+    hipLaunchKernelGGL((k_update6<T, false>), dim3(grid_for(d.N, 1 << 20)), dim3(kThreads), 0, s, e, eps, phase,
+                       coef, d.N);
+}
+
+template <typename T>
+void Launch<T>::stress(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* sigma, long long N,
+                       hipStream_t s) {
+  hipLaunchKernelGGL((k_stress<T>), dim3(grid_for(N, 1 << 20)), dim3(kThreads), 0, s, eps, phase, coef, sigma, N);
+}
+
+void launch_reduce(const double* partials, int nblocks, int nv, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nblocks, nv, out);
+}
+
+#define FE_INSTANTIATE(T)                                                                                 \
+  template void Launch<T>::fill_macro(T*, long long, const double*, hipStream_t);                        \
+  template void Launch<T>::convert_to(T*, const void*, int, long long, hipStream_t);                     \
+  template void Launch<T>::check_phase(const uint8_t*, long long, int, int*, hipStream_t);               \
+  template void Launch<T>::div(const T*, const uint8_t*, const PhaseCoef<T>*, T*, double*, int, Dims, int, \
+                               hipStream_t);                                                              \
+  template void Launch<T>::grad_update(const T*, T*, const uint8_t*, const PhaseCoef<T>*, GreenConst<T>,  \
+                                       Dims, int, int, hipStream_t);                                      \
+  template void Launch<T>::tau6(const T*, const uint8_t*, const PhaseCoef<T>*, T*, int, double*, int, Dims, \
+                                hipStream_t);                                                             \
+  template void Launch<T>::update6(const T*, T*, const uint8_t*, const PhaseCoef<T>*, Dims, int, hipStream_t); \
+  template void Launch<T>::stress(const T*, const uint8_t*, const PhaseCoef<T>*, T*, long long, hipStream_t);
+FE_INSTANTIATE(float)
+FE_INSTANTIATE(double)
+#undef FE_INSTANTIATE
+template void launch_verify_div<float>(const float*, const uint8_t*, const PhaseCoef<double>*, double*, int, Dims, int,
+                                       hipStream_t);
+template void launch_verify_div<double>(const double*, const uint8_t*, const PhaseCoef<double>*, double*, int, Dims,
+                                        int, hipStream_t);
+
+}  // namespace fe

@@ -58,6 +58,7 @@ def _create(lib, nx, ny, nz, disc=2, scheme=1, **kw):
 
 @pytest.mark.parametrize("dims,status", [
     ((14, 16, 16), fe.FE_ERR_UNSUPPORTED),   # 14 = 2 * 7
+    ((16, 36, 16), fe.FE_ERR_UNSUPPORTED),   # 36 = 4 * 9: only 2^a and 3 * 2^a
     ((16, 15, 16), fe.FE_ERR_UNSUPPORTED),   # odd
     ((2048, 16, 16), fe.FE_ERR_UNSUPPORTED),  # above 1024
     ((2, 16, 16), fe.FE_ERR_UNSUPPORTED),

@@ -75,7 +75,7 @@ def test_config1_direct_rotated_fp64_full_solve():
 @pytest.mark.parametrize("scheme", ["DS", "AS"])
 @pytest.mark.parametrize("op", ["MS", "W", "R"])
 def test_equal_iteration_parity_fp64(op, scheme):
-    shape = (24, 16, 36)  # (nz, ny, nx): radix 8,3 / 8,2 / 4,3,3
+    shape = (24, 16, 48)  # (nz, ny, nx): lengths 3*2^3, 2^4, 3*2^4
     phase, E, nu = _three_phase(shape)
     k = 4
     ref = O.solve(phase, E, nu, MACRO, op=op, scheme=scheme, tol=1e-300, max_iter=k)
@@ -88,7 +88,7 @@ def test_equal_iteration_parity_fp64(op, scheme):
 @pytest.mark.parametrize("scheme", ["DS", "AS"])
 @pytest.mark.parametrize("op", ["MS", "W", "R"])
 def test_equal_iteration_parity_fp32(op, scheme):
-    shape = (24, 16, 36)
+    shape = (24, 16, 48)
     phase, E, nu = _three_phase(shape)
     k = 4
     ref = O.solve(phase, E, nu, MACRO, op=op, scheme=scheme, tol=1e-300, max_iter=k)
@@ -101,7 +101,7 @@ def test_equal_iteration_parity_fp32(op, scheme):
     assert abs(res.eta_verify_fp64 - want) <= 1e-9 * want
 
 
-@pytest.mark.parametrize("shape", [(384, 12, 36), (12, 768, 24)])
+@pytest.mark.parametrize("shape", [(384, 12, 48), (12, 768, 24)])
 def test_ragged_tiles_parity_fp64(shape):
     """Grids whose FFT passes end in partial tiles (z-pass column tiles, y-pass
     column tiles, x-pass line blocks)."""
