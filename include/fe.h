@@ -88,6 +88,10 @@ typedef struct {
                              increases of eta (default 50; 0 disables)          */
   int32_t timing;         /* nonzero: time every pass with HIP events on the plan's
                              stream and report it in fe_result.pass_seconds     */
+  int32_t refine;         /* FP32 plans, WP/ROT operators: when the float32 iteration
+                             stalls (or reaches tol while the float64 check does
+                             not), re-anchor in float64 and iterate in float32 on
+                             the correction (default 1; 0 = plain float32)     */
   void* hip_stream;       /* hipStream_t to run on; NULL = the null stream        */
 } fe_plan_options;
 
@@ -147,6 +151,7 @@ typedef struct {
   double seconds;          /* wall time of the iteration loop on the device stream    */
   double pass_seconds[8];  /* with fe_plan_options.timing: summed device time per pass */
   int32_t pass_launches[8];/* with fe_plan_options.timing: launches per pass          */
+  int32_t refinements;     /* float64 re-anchors performed (fe_plan_options.refine)   */
 } fe_result;
 
 /*

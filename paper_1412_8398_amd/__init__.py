@@ -52,6 +52,7 @@ class FePlanOptions(C.Structure):
         ("check_every", C.c_int32),
         ("diverge_window", C.c_int32),
         ("timing", C.c_int32),
+        ("refine", C.c_int32),
         ("hip_stream", C.c_void_p),
     ]
 
@@ -73,6 +74,7 @@ class FeResult(C.Structure):
         ("seconds", C.c_double),
         ("pass_seconds", C.c_double * 8),
         ("pass_launches", C.c_int32 * 8),
+        ("refinements", C.c_int32),
     ]
 
 
@@ -158,6 +160,7 @@ class Result:
     eta_history: np.ndarray = field(default=None, repr=False)
     pass_seconds: dict = field(default=None, repr=False)
     pass_launches: dict = field(default=None, repr=False)
+    refinements: int = 0
 
     @property
     def converged(self) -> bool:
@@ -168,7 +171,8 @@ class Plan:
     """A solver plan for one grid, Green operator and scheme (fe_plan_create)."""
 
     def __init__(self, grid, green="R", scheme="AS", precision="fp32", max_iter=1000, ref_rule="paper",
-                 ds_beta=0.5, E0=0.0, nu0=0.25, check_every=1, diverge_window=50, timing=False, stream=None):
+                 ds_beta=0.5, E0=0.0, nu0=0.25, check_every=1, diverge_window=50, timing=False, refine=True,
+                 stream=None):
         lib = load_library()
         nx, ny, nz = (grid, grid, grid) if isinstance(grid, int) else tuple(grid)
         self.shape = (nz, ny, nx)
@@ -184,6 +188,7 @@ class Plan:
         opt.check_every = int(check_every)
         opt.diverge_window = int(diverge_window)
         opt.timing = 1 if timing else 0
+        opt.refine = 1 if refine else 0
         opt.hip_stream = stream
         h = C.c_void_p()
         s = lib.fe_plan_create(FeGrid(nx, ny, nz), GREEN[green], SCHEME[scheme], C.byref(opt), C.byref(h))
@@ -240,6 +245,7 @@ class Plan:
         res = Result(s, r.iterations, r.eta, r.eta_verify_fp64, np.array(r.mean_stress[:]), r.seconds)
         res.pass_seconds = {n: float(r.pass_seconds[i]) for i, n in enumerate(PASSES)}
         res.pass_launches = {n: int(r.pass_launches[i]) for i, n in enumerate(PASSES)}
+        res.refinements = int(r.refinements)
         if hist is not None:
             res.eta_history = hist[: min(len(hist), r.iterations + 1)]
         return res

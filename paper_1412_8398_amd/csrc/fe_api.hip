@@ -133,6 +133,12 @@ struct fe_plan {
   size_t ws_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t tev[64] = {};  // pass timing pool (pairs)
+  // mixed-precision refinement workspace (allocated on first use)
+  void* dlt = nullptr;       // correction, 6 planes (plan precision)
+  void* rfield = nullptr;    // strain residual of the anchor, 6 planes
+  void* dsig_hi = nullptr;   // divergence of the anchor stress, 3 planes
+  double* d64 = nullptr;     // float64 divergence / displacement, 3 planes
+  cpx<double>* s64 = nullptr;  // float64 half spectra, 3 components
 };
 
 // Optional per-pass timing: HIP events recorded around each launch on the
@@ -183,6 +189,8 @@ extern "C" void fe_plan_options_default(fe_plan_options* o) {
   o->nu0 = 0.25;
   o->check_every = 1;
   o->diverge_window = 50;
+  o->timing = 0;
+  o->refine = 1;
   o->hip_stream = nullptr;
 }
 
@@ -307,7 +315,8 @@ static void free_tables(Tables<T>& t) {
 extern "C" void fe_plan_destroy(fe_plan* p) {
   if (!p) return;
   (void)hipSetDevice(p->device);
-  void* bufs[] = {p->eps_ws, p->R, p->S, p->partials, p->partials2, p->red, p->flag, p->coef, p->coef64};
+  void* bufs[] = {p->eps_ws, p->R,      p->S,       p->partials, p->partials2, p->red, p->flag,
+                  p->coef,   p->coef64, p->dlt,     p->rfield,   p->dsig_hi,   p->d64, p->s64};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_tables(p->t32);
@@ -417,8 +426,8 @@ static fe_status verify_fp64(fe_plan* p, const TS* eps, const uint8_t* phase, do
   hipStream_t s = p->stream;
   const Dims d = p->d;
   if (p->displacement) {
-    launch_verify_div<TS>(eps, phase, p->coef64, p->partials, p->div_blocks, d, p->op, s);
-    launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
+    const int nb = launch_verify_div<TS>(eps, phase, p->coef64, p->partials, d, p->op, s);
+    launch_reduce(p->partials, nb, 7, p->red, s);
     HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     double ms[6];
@@ -518,16 +527,91 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
   const int max_iter = p->opt.max_iter;
   const int every = p->opt.check_every;
 
+  const bool can_refine = p->opt.refine && sizeof(T) == 4 && p->displacement;
+  GreenConst<double> g64;
+  g64.lam0 = ref.lam0;
+  g64.mu0 = ref.mu0;
+  g64.cr = (ref.lam0 + ref.mu0) / (ref.lam0 + 2.0 * ref.mu0);
+  g64.s1 = 1.0 / (2.0 * ref.mu0);
+  g64.s2 = ref.lam0 / (2.0 * ref.mu0 * (3.0 * ref.lam0 + 2.0 * ref.mu0));
+  g64.inv_n = 1.0 / (double)N;
+  for (int i = 0; i < 6; ++i) g64.macro[i] = macro[i];
+
+  // State: without an anchor the iterate is eps itself; with an anchor the
+  // strain is eps + it, where it = correction (it starts at 0 at each re-anchor)
+  // and the anchor's strain residual rf and stress divergence dbase come from
+  // float64 arithmetic.
+  T* it = eps;
+  const T* rf = nullptr;
+  const T* dbase = nullptr;
+  double mean_hi[6] = {0, 0, 0, 0, 0, 0};
+  bool anchored = false;
+  int refinements = 0;
+
+  // float64 re-anchor at the strain eps (+ it if anchored)
+  auto reanchor = [&]() -> fe_status {
+    const size_t spec = (size_t)d.H * d.ny * d.nx;
+    if (!p->dlt) {
+      HIP_TRY(dmalloc(p, &p->dlt, 6 * (size_t)N * sizeof(T)));
+      HIP_TRY(dmalloc(p, &p->rfield, 6 * (size_t)N * sizeof(T)));
+      HIP_TRY(dmalloc(p, &p->dsig_hi, 3 * (size_t)N * sizeof(T)));
+      HIP_TRY(dmalloc(p, (void**)&p->d64, 3 * (size_t)N * sizeof(double)));
+      HIP_TRY(dmalloc(p, (void**)&p->s64, 3 * spec * sizeof(cpx<double>)));
+    }
+    if (anchored) Launch<T>::axpy(eps, it, 6 * N, s);
+    const int nb = launch_div64<T>(eps, phase, p->coef64, p->d64, static_cast<T*>(p->dsig_hi), p->partials, d,
+                                   p->op, s);
+    launch_reduce(p->partials, nb, 7, p->red, s);
+    const Tables<double>& t = p->t64;
+    Launch<double>::zr2c(p->d64, p->s64, 3, d, t.tw[2], s);
+    Launch<double>::yfft(p->s64, 3, d, t.tw[1], 0, s);
+    Launch<double>::xgreen3(p->s64, d, t.tw[0], wave_tables<double>(p), g64, p->op, s);
+    Launch<double>::yfft(p->s64, 3, d, t.tw[1], 1, s);
+    Launch<double>::zc2r(p->s64, p->d64, 3, d, t.tw[2], s);
+    launch_residual<T>(p->d64, eps, g64, static_cast<T*>(p->rfield), d, p->op, s);
+    HIP_TRY(hipMemsetAsync(p->dlt, 0, 6 * (size_t)N * sizeof(T), s));
+    HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < 6; ++i) mean_hi[i] = p->h_red[1 + i] / (double)N;
+    it = static_cast<T*>(p->dlt);
+    rf = static_cast<const T*>(p->rfield);
+    dbase = static_cast<const T*>(p->dsig_hi);
+    anchored = true;
+    ++refinements;
+    return FE_OK;
+  };
+  // float64 eta of the strain eps (+ it if anchored), folding it into eps
+  auto verify_total = [&](double* ev) -> fe_status {
+    if (anchored) {
+      Launch<T>::axpy(eps, it, 6 * N, s);
+      HIP_TRY(hipMemsetAsync(it, 0, 6 * (size_t)N * sizeof(T), s));
+    }
+    return verify_fp64<T>(p, eps, phase, ev);
+  };
+
   HIP_TRY(hipEventRecord(p->ev0, s));
   PassTimer tm(p, p->opt.timing != 0);
   fe_status status = FE_NOT_CONVERGED;
   double eta = NAN, prev_eta = INFINITY, mean[6] = {0, 0, 0, 0, 0, 0};
-  int rising = 0, k = 0;
+  double verified = NAN, last_verified = INFINITY;
+  const int W = 10;
+  std::vector<double> hist;
+  int rising = 0, k = 0, last_anchor = 0;
+  bool need_anchor = false;
   for (k = 0;; ++k) {
+    if (need_anchor) {
+      fe_status rs = reanchor();
+      if (rs != FE_OK) return rs;
+      need_anchor = false;
+      last_anchor = k;
+      rising = 0;
+      prev_eta = INFINITY;
+    }
     const bool check = (k % every == 0) || k == max_iter;
     if (p->displacement) {
-      tm.run(FE_PASS_POINTWISE, [&] { Launch<T>::div(eps, phase, coef, R, p->partials, p->div_blocks, d, p->op, s); });
-      if (check) tm.run(FE_PASS_ETA, [&] { launch_reduce(p->partials, p->div_blocks, 7, p->red, s); });
+      int nb = 0;
+      tm.run(FE_PASS_POINTWISE, [&] { nb = Launch<T>::div(it, phase, coef, R, dbase, p->partials, d, p->op, s); });
+      if (check) tm.run(FE_PASS_ETA, [&] { launch_reduce(p->partials, nb, 7, p->red, s); });
     } else if (check) {
       tm.run(FE_PASS_ETA, [&] {
         Launch<T>::tau6(eps, phase, coef, R, 1, p->partials, p->div_blocks, d, s);
@@ -542,17 +626,41 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       tm.flush();
-      for (int i = 0; i < 6; ++i) mean[i] = p->h_red[1 + i] / (double)N;
+      for (int i = 0; i < 6; ++i) mean[i] = mean_hi[i] + p->h_red[1 + i] / (double)N;
       const double nrm = frob(mean);
       eta = p->displacement ? std::sqrt(p->h_red[0] / (double)N) / nrm : std::sqrt(p->h_red[8]) / ((double)N * nrm);
       if (out->eta_history && k < out->history_capacity) out->eta_history[k] = eta;
+      hist.push_back(eta);
       if (!std::isfinite(eta)) {
         status = FE_DIVERGED;
         break;
       }
       if (eta <= tol) {
-        status = FE_OK;
-        break;
+        if (!can_refine) {
+          status = FE_OK;
+          break;
+        }
+        // the float32 measure says converged: confirm in float64
+        fe_status vs = verify_total(&verified);
+        if (vs != FE_OK) return vs;
+        if (verified <= tol) {
+          status = FE_OK;
+          break;
+        }
+        // not there in float64.  If the previous float64 check was no worse,
+        // the float32-stored strain cannot get closer (storage floor): stop.
+        if (verified > 0.9 * last_verified) {
+          status = FE_NOT_CONVERGED;
+          break;
+        }
+        last_verified = verified;
+        // re-anchor at this strain and redo this iteration from the new anchor
+        // (at most once per anchor)
+        if (k > last_anchor || !anchored) {
+          need_anchor = true;
+          --k;
+          continue;
+        }
       }
       if (k >= max_iter) {
         status = FE_NOT_CONVERGED;
@@ -560,7 +668,15 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       }
       rising = eta > prev_eta ? rising + 1 : 0;
       prev_eta = eta;
-      if (p->opt.diverge_window > 0 && rising >= p->opt.diverge_window) {
+      if (p->opt.diverge_window > 0 && rising >= p->opt.diverge_window && !can_refine) {
+        status = FE_DIVERGED;
+        break;
+      }
+      // stagnation of the float32 iteration: less than 30% decrease over W checks
+      const int nh = (int)hist.size();
+      if (can_refine && !need_anchor && k - last_anchor >= 2 * W && nh > W && eta > 0.7 * hist[nh - 1 - W])
+        need_anchor = true;
+      if (can_refine && p->opt.diverge_window > 0 && rising >= p->opt.diverge_window && refinements > 3) {
         status = FE_DIVERGED;
         break;
       }
@@ -571,7 +687,7 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen3(S, d, tb.tw[0], wt, g, p->op, s); });
       tm.run(FE_PASS_YINV, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], 1, s); });
       tm.run(FE_PASS_ZINV, [&] { Launch<T>::zc2r(S, R, 3, d, tb.tw[2], s); });
-      tm.run(FE_PASS_UPDATE, [&] { Launch<T>::grad_update(R, eps, phase, coef, g, d, p->op, accel, s); });
+      tm.run(FE_PASS_UPDATE, [&] { Launch<T>::grad_update(R, it, phase, coef, g, rf, d, p->op, accel, s); });
     } else {
       tm.run(FE_PASS_POINTWISE, [&] { Launch<T>::tau6(eps, phase, coef, R, 0, nullptr, p->div_blocks, d, s); });
       tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 6, d, tb.tw[2], s); });
@@ -583,6 +699,10 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     }
     HIP_TRY(hipGetLastError());
   }
+  if (anchored) {  // the returned strain is anchor + correction
+    Launch<T>::axpy(eps, it, 6 * N, s);
+    HIP_TRY(hipMemsetAsync(it, 0, 6 * (size_t)N * sizeof(T), s));
+  }
   HIP_TRY(hipEventRecord(p->ev1, s));
   HIP_TRY(hipEventSynchronize(p->ev1));
   tm.flush();
@@ -593,6 +713,7 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     out->pass_seconds[i] = tm.sec[i];
     out->pass_launches[i] = tm.launches[i];
   }
+  out->refinements = refinements;
 
   if (out->stress) Launch<T>::stress(eps, phase, coef, static_cast<T*>(out->stress), N, s);
   double ev = eta;

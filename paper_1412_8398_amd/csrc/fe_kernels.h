@@ -51,10 +51,15 @@ struct Launch {
   static void check_phase(const uint8_t* phase, long long N, int n_phases, int* flag, hipStream_t s);
 
   // Displacement form (WP and ROT operators).
-  static void div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, double* partials,
-                  int nblocks, Dims d, int op, hipStream_t s);
+  // Writes the divergence of tau to D; Dsig_base (nullable) is added to the
+  // divergence of sigma before eta's reduction.  Returns the number of partial
+  // sums (7 doubles each) written.
+  static int div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, const T* Dsig_base,
+                 double* partials, Dims d, int op, hipStream_t s);
+  // rfield (nullable, 6 planes) replaces the constant applied strain.
   static void grad_update(const T* U, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef,
-                          GreenConst<T> g, Dims d, int op, int accelerated, hipStream_t s);
+                          GreenConst<T> g, const T* rfield, Dims d, int op, int accelerated, hipStream_t s);
+  static void axpy(T* y, const T* x, long long n, hipStream_t s);  // y += x
   static void xgreen3(cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> wt, GreenConst<T> g, int op,
                       hipStream_t s);
 
@@ -79,9 +84,20 @@ struct Launch {
 };
 
 // float64 verification of eta from a strain of storage type TS (ROT, WP).
+// Returns the number of partial sums (7 doubles each) written.
 template <typename TS>
-void launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* partials,
-                       int nblocks, Dims d, int op, hipStream_t s);
+int launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* partials, Dims d,
+                      int op, hipStream_t s);
+
+// float64 divergences of an anchor strain: Dtau (float64, nullable) and Dsig
+// (storage type, nullable); partial sums as in Launch::div.
+template <typename TS>
+int launch_div64(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* Dtau, TS* Dsig,
+                 double* partials, Dims d, int op, hipStream_t s);
+
+// r = eps_bar + sym grad_h U - eps in float64 arithmetic (U float64).
+template <typename TE>
+void launch_residual(const double* U, const TE* eps, GreenConst<double> g, TE* r, Dims d, int op, hipStream_t s);
 
 void launch_reduce(const double* partials, int nblocks, int nv, double* out, hipStream_t s);
 

@@ -32,6 +32,8 @@ __device__ __forceinline__ void iso_apply(T lam, T mu, const T (&e)[6], T (&s)[6
 }
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// periodic index for any i >= -n
+__device__ __forceinline__ int pmod(int i, int n) { return (i + n) % n; }
 
 // --------------------------------------------------------------------------
 // initialisation, checks, conversions
@@ -80,102 +82,148 @@ static int grid_for(long long n, int cap = 8192) {
 // float64 (eq. (43) and eq. (5)).
 // --------------------------------------------------------------------------
 
-template <typename TS, typename TC, int OP, bool WRITE_D>
-__global__ __launch_bounds__(256) void k_div(const TS* __restrict__ eps, const uint8_t* __restrict__ phase,
-                                             const PhaseCoef<TC>* __restrict__ coef, TS* __restrict__ D,
-                                             double* __restrict__ partials, Dims d) {
+// The corner stencil is separable.  With S_l f(c) = f(c) + f(c - e_l) and
+// D_l f(c) = f(c - e_l) - f(c),
+//   D_j = 1/4 [ S_z (D_x S_y s_xj + S_x D_y s_yj) + D_z (S_x S_y s_zj) ],
+// so a workgroup walks a DX x DY tile of corners along z, loads each voxel
+// plane (with a one-voxel halo at -x, -y) once into LDS as tau and sigma, and
+// keeps the in-plane combinations P = 1/4 (D_x S_y s_xj + S_x D_y s_yj) and
+// Q = 1/4 S_x S_y s_zj of the previous plane in registers:
+//   D_j(z) = P(z) + P(z-1) + Q(z-1) - Q(z).
+// WP uses the same walk with P = [s_xj(x) - s_xj(x-e_x)] + [s_yj(x) - s_yj(x-e_y)],
+// Q = s_zj(x): D_j(z) = P(z) + Q(z) - Q(z-1).
+constexpr int DX = 32, DY = 8;
+
+// Optional outputs/inputs (null to skip): Dtau receives the divergence of tau
+// (type TD), Dsig the divergence of sigma (type TS), and Dsig_base is added to
+// the divergence of sigma before it is squared for eta (the divergence of an
+// anchor strain when iterating on a correction).
+template <typename TS, typename TC, typename TD, int OP>
+__global__ __launch_bounds__(DX * DY) void k_div(const TS* __restrict__ eps, const uint8_t* __restrict__ phase,
+                                                 const PhaseCoef<TC>* __restrict__ coef, TD* __restrict__ Dtau,
+                                                 TS* __restrict__ Dsig, const TS* __restrict__ Dsig_base,
+                                                 double* __restrict__ partials, Dims d, int zchunk) {
+  __shared__ TC st[DY + 1][DX + 1][6];
+  __shared__ TC ss[DY + 1][DX + 1][6];
   __shared__ double red[7 * 16];
   const long long N = d.N;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const int ntx = (nx + DX - 1) / DX, nty = (ny + DY - 1) / DY;
+  const int bx = blockIdx.x % ntx;
+  const int rest = blockIdx.x / ntx;
+  const int by = rest % nty;
+  const int bz = rest / nty;
+  const int x0 = bx * DX, y0 = by * DY, z0 = bz * zchunk;
+  const int z1 = min(nz, z0 + zchunk);
+  const int tx = threadIdx.x % DX, ty = threadIdx.x / DX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool own = x < nx && y < ny;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(c % nx);
-    const int y = (int)((c / nx) % ny);
-    const int z = (int)(c / ((long long)nx * ny));
-    TC Dt[3] = {0, 0, 0}, Ds[3] = {0, 0, 0};
-    if (OP == OP_ROT) {
+  TC pt[3] = {0, 0, 0}, qt[3] = {0, 0, 0}, ps[3] = {0, 0, 0}, qs[3] = {0, 0, 0};
+  for (int zz = z0 - 1; zz < z1; ++zz) {
+    const int z = zz < 0 ? zz + nz : zz;
+    for (int idx = threadIdx.x; idx < (DX + 1) * (DY + 1); idx += DX * DY) {
+      const int i = idx % (DX + 1), j = idx / (DX + 1);
+      const int xv = pmod(x0 - 1 + i, nx), yv = pmod(y0 - 1 + j, ny);
+      const long long v = ((long long)z * ny + yv) * nx + xv;
+      TC e[6];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-        const long long v = ((long long)wrap(z - az, nz) * ny + wrap(y - ay, ny)) * nx + wrap(x - ax, nx);
-        TC e[6];
+      for (int k = 0; k < 6; ++k) e[k] = TC(eps[k * N + v]);
+      const PhaseCoef<TC> pc = coef[phase[v]];
+      TC t[6], sg[6];
+      iso_apply(pc.dlam, pc.dmu, e, t);
+      iso_apply(pc.lam, pc.mu, e, sg);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) e[k] = TC(eps[k * N + v]);
-        const PhaseCoef<TC> pc = coef[phase[v]];
-        TC t[6], s[6];
-        iso_apply(pc.dlam, pc.dmu, e, t);
-        iso_apply(pc.lam, pc.mu, e, s);
-        const int sg[3] = {ax ? 1 : -1, ay ? 1 : -1, az ? 1 : -1};
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            const int q = voigt_of(i, j);
-            Dt[j] += sg[i] * t[q];
-            Ds[j] += sg[i] * s[q];
-          }
-        }
-        if (a == 0) {
-#pragma unroll
-          for (int k = 0; k < 6; ++k) acc[1 + k] += double(s[k]);
-        }
+      for (int k = 0; k < 6; ++k) {
+        st[j][i][k] = t[k];
+        ss[j][i][k] = sg[k];
       }
+    }
+    __syncthreads();
+    // voxel c - a for a in {0,1}^2 in the plane: (tx+1-ax, ty+1-ay)
+    TC Pt[3], Qt[3], Ps[3], Qs[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int cx = voigt_of(0, j), cy = voigt_of(1, j), cz = voigt_of(2, j);
+      if (OP == OP_ROT) {
+        // f(c), f(c-ex), f(c-ey), f(c-ex-ey)
+        const TC ax0 = st[ty + 1][tx + 1][cx], ax1 = st[ty + 1][tx][cx], ax2 = st[ty][tx + 1][cx], ax3 = st[ty][tx][cx];
+        const TC ay0 = st[ty + 1][tx + 1][cy], ay1 = st[ty + 1][tx][cy], ay2 = st[ty][tx + 1][cy], ay3 = st[ty][tx][cy];
+        const TC az0 = st[ty + 1][tx + 1][cz], az1 = st[ty + 1][tx][cz], az2 = st[ty][tx + 1][cz], az3 = st[ty][tx][cz];
+        Pt[j] = TC(0.25) * (((ax1 + ax3) - (ax0 + ax2)) + ((ay2 + ay3) - (ay0 + ay1)));
+        Qt[j] = TC(0.25) * ((az0 + az1) + (az2 + az3));
+        const TC bx0 = ss[ty + 1][tx + 1][cx], bx1 = ss[ty + 1][tx][cx], bx2 = ss[ty][tx + 1][cx], bx3 = ss[ty][tx][cx];
+        const TC by0 = ss[ty + 1][tx + 1][cy], by1 = ss[ty + 1][tx][cy], by2 = ss[ty][tx + 1][cy], by3 = ss[ty][tx][cy];
+        const TC bz0 = ss[ty + 1][tx + 1][cz], bz1 = ss[ty + 1][tx][cz], bz2 = ss[ty][tx + 1][cz], bz3 = ss[ty][tx][cz];
+        Ps[j] = TC(0.25) * (((bx1 + bx3) - (bx0 + bx2)) + ((by2 + by3) - (by0 + by1)));
+        Qs[j] = TC(0.25) * ((bz0 + bz1) + (bz2 + bz3));
+      } else {
+        Pt[j] = (st[ty + 1][tx + 1][cx] - st[ty + 1][tx][cx]) + (st[ty + 1][tx + 1][cy] - st[ty][tx + 1][cy]);
+        Qt[j] = st[ty + 1][tx + 1][cz];
+        Ps[j] = (ss[ty + 1][tx + 1][cx] - ss[ty + 1][tx][cx]) + (ss[ty + 1][tx + 1][cy] - ss[ty][tx + 1][cy]);
+        Qs[j] = ss[ty + 1][tx + 1][cz];
+      }
+    }
+    if (zz >= z0 && own) {
+      const long long c = ((long long)z * ny + y) * nx + x;
+      TC Dt[3], Ds[3];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        Dt[j] *= TC(0.25);
-        Ds[j] *= TC(0.25);
-      }
-    } else {  // OP_WP
-      {
-        TC e[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) e[k] = TC(eps[k * N + c]);
-        const PhaseCoef<TC> pc = coef[phase[c]];
-        TC t[6], s[6];
-        iso_apply(pc.dlam, pc.dmu, e, t);
-        iso_apply(pc.lam, pc.mu, e, s);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            Dt[j] += t[voigt_of(i, j)];
-            Ds[j] += s[voigt_of(i, j)];
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < 6; ++k) acc[1 + k] += double(s[k]);
-      }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int xm = i == 0 ? wrap(x - 1, nx) : x;
-        const int ym = i == 1 ? wrap(y - 1, ny) : y;
-        const int zm = i == 2 ? wrap(z - 1, nz) : z;
-        const long long v = ((long long)zm * ny + ym) * nx + xm;
-        TC e[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) e[k] = TC(eps[k * N + v]);
-        const PhaseCoef<TC> pc = coef[phase[v]];
-        TC t[6], s[6];
-        iso_apply(pc.dlam, pc.dmu, e, t);
-        iso_apply(pc.lam, pc.mu, e, s);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          Dt[j] -= t[voigt_of(i, j)];
-          Ds[j] -= s[voigt_of(i, j)];
+        if (OP == OP_ROT) {
+          Dt[j] = (Pt[j] + pt[j]) + (qt[j] - Qt[j]);
+          Ds[j] = (Ps[j] + ps[j]) + (qs[j] - Qs[j]);
+        } else {
+          Dt[j] = Pt[j] + (Qt[j] - qt[j]);
+          Ds[j] = Ps[j] + (Qs[j] - qs[j]);
         }
       }
-    }
-    if (WRITE_D) {
+      if (Dtau) {
 #pragma unroll
-      for (int j = 0; j < 3; ++j) D[j * N + c] = TS(Dt[j]);
+        for (int j = 0; j < 3; ++j) Dtau[j * N + c] = TD(Dt[j]);
+      }
+      if (Dsig) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Dsig[j * N + c] = TS(Ds[j]);
+      }
+      double q[3] = {double(Ds[0]), double(Ds[1]), double(Ds[2])};
+      if (Dsig_base) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) q[j] += double(Dsig_base[j * N + c]);
+      }
+      acc[0] += q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[1 + k] += double(ss[ty + 1][tx + 1][k]);
     }
-    acc[0] += double(Ds[0]) * double(Ds[0]) + double(Ds[1]) * double(Ds[1]) + double(Ds[2]) * double(Ds[2]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      pt[j] = Pt[j];
+      qt[j] = Qt[j];
+      ps[j] = Ps[j];
+      qs[j] = Qs[j];
+    }
+    __syncthreads();
   }
   block_sum<7>(acc, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < 7; ++i) partials[blockIdx.x * 7 + i] = acc[i];
   }
+}
+
+// Tiling of the divergence walk: DX x DY corner tiles, z cut into chunks so
+// that there are at least 2048 workgroups (at most 4096 partial sums).
+struct DivGrid {
+  int blocks, zchunk;
+};
+static DivGrid div_grid(const Dims& d) {
+  const int ntx = (d.nx + DX - 1) / DX, nty = (d.ny + DY - 1) / DY;
+  const int bxy = ntx * nty;
+  int nch = (2048 + bxy - 1) / bxy;
+  if (nch > d.nz) nch = d.nz;
+  if (nch < 1) nch = 1;
+  const int zchunk = (d.nz + nch - 1) / nch;
+  nch = (d.nz + zchunk - 1) / zchunk;
+  return DivGrid{bxy * nch, zchunk};
 }
 
 // --------------------------------------------------------------------------
@@ -187,11 +235,14 @@ __global__ __launch_bounds__(256) void k_div(const TS* __restrict__ eps, const u
 // AS (eq. (16)): eps <- eps + 2 kappa0/(kappa+kappa0) sph(e - eps) + 2 mu0/(mu+mu0) dev(e - eps).
 // --------------------------------------------------------------------------
 
+// With rfield non-null the applied strain is the field rfield (6 planes)
+// instead of the constant eps_bar: the update of a correction whose anchor
+// strain has the strain residual rfield.
 template <typename T, int OP, bool AS>
 __global__ __launch_bounds__(256) void k_grad_update(const T* __restrict__ U, T* __restrict__ eps,
                                                      const uint8_t* __restrict__ phase,
                                                      const PhaseCoef<T>* __restrict__ coef, GreenConst<T> g,
-                                                     Dims d) {
+                                                     const T* __restrict__ rfield, Dims d) {
   const long long N = d.N;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
@@ -231,13 +282,16 @@ __global__ __launch_bounds__(256) void k_grad_update(const T* __restrict__ U, T*
         for (int j = 0; j < 3; ++j) gr[i][j] = U[j * N + c] - u0[j];
       }
     }
+    T base[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) base[k] = rfield ? rfield[k * N + v] : g.macro[k];
     T e[6];
-    e[0] = g.macro[0] + gr[0][0];
-    e[1] = g.macro[1] + gr[1][1];
-    e[2] = g.macro[2] + gr[2][2];
-    e[3] = g.macro[3] + T(0.5) * (gr[1][2] + gr[2][1]);
-    e[4] = g.macro[4] + T(0.5) * (gr[0][2] + gr[2][0]);
-    e[5] = g.macro[5] + T(0.5) * (gr[0][1] + gr[1][0]);
+    e[0] = base[0] + gr[0][0];
+    e[1] = base[1] + gr[1][1];
+    e[2] = base[2] + gr[2][2];
+    e[3] = base[3] + T(0.5) * (gr[1][2] + gr[2][1]);
+    e[4] = base[4] + T(0.5) * (gr[0][2] + gr[2][0]);
+    e[5] = base[5] + T(0.5) * (gr[0][1] + gr[1][0]);
     if (AS) {
       const PhaseCoef<T> pc = coef[phase[v]];
       T cur[6], dd[6];
@@ -256,6 +310,65 @@ __global__ __launch_bounds__(256) void k_grad_update(const T* __restrict__ U, T*
       for (int k = 0; k < 6; ++k) eps[k * N + v] = e[k];
     }
   }
+}
+
+// Strain residual of an anchor strain in float64 arithmetic:
+// r = eps_bar + sym grad_h U - eps (U from the float64 transforms of the
+// divergence of (C - C0):eps), stored in the anchor's precision.
+template <typename TE, int OP>
+__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ U, const TE* __restrict__ eps,
+                                                  GreenConst<double> g, TE* __restrict__ r, Dims d) {
+  const long long N = d.N;
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(v % nx);
+    const int y = (int)((v / nx) % ny);
+    const int z = (int)(v / ((long long)nx * ny));
+    double gr[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) gr[i][j] = 0.0;
+    if (OP == OP_ROT) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+        const long long c = ((long long)wrap(z + az, nz) * ny + wrap(y + ay, ny)) * nx + wrap(x + ax, nx);
+        const double u[3] = {U[c], U[N + c], U[2 * N + c]};
+        const double sg[3] = {ax ? 1.0 : -1.0, ay ? 1.0 : -1.0, az ? 1.0 : -1.0};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) gr[i][j] += sg[i] * u[j];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gr[i][j] *= 0.25;
+    } else {
+      const double u0[3] = {U[v], U[N + v], U[2 * N + v]};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int xp = i == 0 ? wrap(x + 1, nx) : x;
+        const int yp = i == 1 ? wrap(y + 1, ny) : y;
+        const int zp = i == 2 ? wrap(z + 1, nz) : z;
+        const long long c = ((long long)zp * ny + yp) * nx + xp;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gr[i][j] = U[j * N + c] - u0[j];
+      }
+    }
+    const double e[6] = {g.macro[0] + gr[0][0], g.macro[1] + gr[1][1], g.macro[2] + gr[2][2],
+                         g.macro[3] + 0.5 * (gr[1][2] + gr[2][1]), g.macro[4] + 0.5 * (gr[0][2] + gr[2][0]),
+                         g.macro[5] + 0.5 * (gr[0][1] + gr[1][0])};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r[k * N + v] = TE(e[k] - double(eps[k * N + v]));
+  }
+}
+
+template <typename T>
+__global__ void k_axpy(T* __restrict__ y, const T* __restrict__ x, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] += x[i];
 }
 
 // --------------------------------------------------------------------------
@@ -369,42 +482,66 @@ void Launch<T>::check_phase(const uint8_t* phase, long long N, int n_phases, int
 }
 
 template <typename T>
-void Launch<T>::div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, double* partials,
-                    int nblocks, Dims d, int op, hipStream_t s) {
+int Launch<T>::div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, const T* Dsig_base,
+                   double* partials, Dims d, int op, hipStream_t s) {
+  const DivGrid gd = div_grid(d);
   if (op == OP_ROT)
-    hipLaunchKernelGGL((k_div<T, T, OP_ROT, true>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef, D,
-                       partials, d);
+    hipLaunchKernelGGL((k_div<T, T, T, OP_ROT>), dim3(gd.blocks), dim3(DX * DY), 0, s, eps, phase, coef, D,
+                       (T*)nullptr, Dsig_base, partials, d, gd.zchunk);
   else
-    hipLaunchKernelGGL((k_div<T, T, OP_WP, true>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef, D,
-                       partials, d);
+    hipLaunchKernelGGL((k_div<T, T, T, OP_WP>), dim3(gd.blocks), dim3(DX * DY), 0, s, eps, phase, coef, D,
+                       (T*)nullptr, Dsig_base, partials, d, gd.zchunk);
+  return gd.blocks;
 }
 
 template <typename TS>
-void launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* partials,
-                       int nblocks, Dims d, int op, hipStream_t s) {
+int launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* partials, Dims d,
+                      int op, hipStream_t s) {
+  return launch_div64(eps, phase, coef, nullptr, (TS*)nullptr, partials, d, op, s);
+}
+
+template <typename TS>
+int launch_div64(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* Dtau, TS* Dsig,
+                 double* partials, Dims d, int op, hipStream_t s) {
+  const DivGrid gd = div_grid(d);
   if (op == OP_ROT)
-    hipLaunchKernelGGL((k_div<TS, double, OP_ROT, false>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef,
-                       (TS*)nullptr, partials, d);
+    hipLaunchKernelGGL((k_div<TS, double, double, OP_ROT>), dim3(gd.blocks), dim3(DX * DY), 0, s, eps, phase, coef,
+                       Dtau, Dsig, (const TS*)nullptr, partials, d, gd.zchunk);
   else
-    hipLaunchKernelGGL((k_div<TS, double, OP_WP, false>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef,
-                       (TS*)nullptr, partials, d);
+    hipLaunchKernelGGL((k_div<TS, double, double, OP_WP>), dim3(gd.blocks), dim3(DX * DY), 0, s, eps, phase, coef,
+                       Dtau, Dsig, (const TS*)nullptr, partials, d, gd.zchunk);
+  return gd.blocks;
 }
 
 template <typename T>
 void Launch<T>::grad_update(const T* U, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, GreenConst<T> g,
-                            Dims d, int op, int accelerated, hipStream_t s) {
+                            const T* rfield, Dims d, int op, int accelerated, hipStream_t s) {
   const dim3 gr(grid_for(d.N, 1 << 20)), bl(kThreads);
   if (op == OP_ROT) {
     if (accelerated)
-      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, true>), gr, bl, 0, s, U, eps, phase, coef, g, d);
+      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, true>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d);
     else
-      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, false>), gr, bl, 0, s, U, eps, phase, coef, g, d);
+      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, false>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d);
   } else {
     if (accelerated)
-      hipLaunchKernelGGL((k_grad_update<T, OP_WP, true>), gr, bl, 0, s, U, eps, phase, coef, g, d);
+      hipLaunchKernelGGL((k_grad_update<T, OP_WP, true>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d);
     else
-      hipLaunchKernelGGL((k_grad_update<T, OP_WP, false>), gr, bl, 0, s, U, eps, phase, coef, g, d);
+      hipLaunchKernelGGL((k_grad_update<T, OP_WP, false>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d);
   }
+}
+
+template <typename TE>
+void launch_residual(const double* U, const TE* eps, GreenConst<double> g, TE* r, Dims d, int op, hipStream_t s) {
+  const dim3 gr(grid_for(d.N, 1 << 20)), bl(kThreads);
+  if (op == OP_ROT)
+    hipLaunchKernelGGL((k_residual<TE, OP_ROT>), gr, bl, 0, s, U, eps, g, r, d);
+  else
+    hipLaunchKernelGGL((k_residual<TE, OP_WP>), gr, bl, 0, s, U, eps, g, r, d);
+}
+
+template <typename T>
+void Launch<T>::axpy(T* y, const T* x, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_axpy<T>), dim3(grid_for(n, 1 << 20)), dim3(kThreads), 0, s, y, x, n);
 }
 
 template <typename T>
@@ -439,10 +576,11 @@ void launch_reduce(const double* partials, int nblocks, int nv, double* out, hip
   template void Launch<T>::fill_macro(T*, long long, const double*, hipStream_t);                        \
   template void Launch<T>::convert_to(T*, const void*, int, long long, hipStream_t);                     \
   template void Launch<T>::check_phase(const uint8_t*, long long, int, int*, hipStream_t);               \
-  template void Launch<T>::div(const T*, const uint8_t*, const PhaseCoef<T>*, T*, double*, int, Dims, int, \
-                               hipStream_t);                                                              \
+  template int Launch<T>::div(const T*, const uint8_t*, const PhaseCoef<T>*, T*, const T*, double*, Dims, int, \
+                              hipStream_t);                                                               \
+  template void Launch<T>::axpy(T*, const T*, long long, hipStream_t);                                     \
   template void Launch<T>::grad_update(const T*, T*, const uint8_t*, const PhaseCoef<T>*, GreenConst<T>,  \
-                                       Dims, int, int, hipStream_t);                                      \
+                                       const T*, Dims, int, int, hipStream_t);                            \
   template void Launch<T>::tau6(const T*, const uint8_t*, const PhaseCoef<T>*, T*, int, double*, int, Dims, \
                                 hipStream_t);                                                             \
   template void Launch<T>::update6(const T*, T*, const uint8_t*, const PhaseCoef<T>*, Dims, int, hipStream_t); \
@@ -450,9 +588,16 @@ void launch_reduce(const double* partials, int nblocks, int nv, double* out, hip
 FE_INSTANTIATE(float)
 FE_INSTANTIATE(double)
 #undef FE_INSTANTIATE
-template void launch_verify_div<float>(const float*, const uint8_t*, const PhaseCoef<double>*, double*, int, Dims, int,
+template int launch_verify_div<float>(const float*, const uint8_t*, const PhaseCoef<double>*, double*, Dims, int,
+                                      hipStream_t);
+template int launch_verify_div<double>(const double*, const uint8_t*, const PhaseCoef<double>*, double*, Dims, int,
                                        hipStream_t);
-template void launch_verify_div<double>(const double*, const uint8_t*, const PhaseCoef<double>*, double*, int, Dims,
-                                        int, hipStream_t);
+template int launch_div64<float>(const float*, const uint8_t*, const PhaseCoef<double>*, double*, float*, double*,
+                                 Dims, int, hipStream_t);
+template int launch_div64<double>(const double*, const uint8_t*, const PhaseCoef<double>*, double*, double*, double*,
+                                  Dims, int, hipStream_t);
+template void launch_residual<float>(const double*, const float*, GreenConst<double>, float*, Dims, int, hipStream_t);
+template void launch_residual<double>(const double*, const double*, GreenConst<double>, double*, Dims, int,
+                                      hipStream_t);
 
 }  // namespace fe
