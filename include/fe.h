@@ -181,6 +181,44 @@ fe_status fe_solve(fe_plan* plan, const uint8_t* phase, fe_materials materials,
 fe_status fe_effective_stiffness(fe_plan* plan, const uint8_t* phase, fe_materials materials,
                                  double tol, double C_voigt[36], int32_t iterations[6]);
 
+/*
+ * Batched solves of many independent microstructures (possibly of different
+ * grid sizes) with one operator and scheme, e.g. to generate training data.
+ * Samples are grouped by grid; each pass of an iteration is one launch over
+ * all active samples of a group (the sample is the second grid dimension of
+ * the launch), eta is reduced per sample on the device, and a sample retires
+ * as soon as its own eta^k <= tol (or its iteration cap is reached).
+ * Supported: FE_GREEN_WP and FE_GREEN_ROT (displacement form); plain
+ * iterations in the plan precision (no float64 re-anchoring).
+ *   desc->phase[i]   device, N_i uint8 labels of sample i
+ *   desc->strain[i]  device, 6*N_i of the requested precision, receives eps of
+ *                    sample i (NULL: not returned)
+ *   results          host, n_samples entries
+ *   seconds          host, may be NULL: device time of the iteration loops
+ * Returns FE_OK if every sample converged, FE_NOT_CONVERGED / FE_DIVERGED if
+ * some did not (see results[i].status), or an error (nothing written).
+ */
+typedef struct {
+  int32_t n_samples;
+  const fe_grid* grids;          /* host, n_samples                              */
+  const uint8_t* const* phase;   /* host array of n_samples device pointers      */
+  const fe_materials* materials; /* host, n_samples                              */
+  const double* macro_strain;    /* host, 6*n_samples, tensor Voigt order       */
+  void* const* strain;           /* host array of n_samples device pointers or NULL */
+} fe_batch_desc;
+
+typedef struct {
+  int32_t status;          /* fe_status of this sample                           */
+  int32_t iterations;
+  double eta;              /* eta at the returned iterate, float64 reduction    */
+  double eta_verify_fp64;  /* eta recomputed with float64 arithmetic            */
+  double mean_stress[6];
+} fe_batch_result;
+
+fe_status fe_solve_batched(fe_discretization disc, fe_scheme scheme, const fe_plan_options* opt,
+                           const fe_batch_desc* desc, double tol, fe_batch_result* results,
+                           double* seconds);
+
 /* Human-readable name of a status code (static string). */
 const char* fe_status_string(fe_status s);
 

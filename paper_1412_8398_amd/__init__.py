@@ -17,7 +17,7 @@ import numpy as np
 __all__ = [
     "FE_OK", "FE_NOT_CONVERGED", "FE_DIVERGED", "FE_ERR_INVALID_ARG", "FE_ERR_UNSUPPORTED",
     "FE_ERR_OOM", "FE_ERR_DEVICE", "GREEN", "SCHEME", "PRECISION", "FeError", "Plan", "Result",
-    "load_library", "library_path", "status_string", "last_error",
+    "load_library", "library_path", "status_string", "last_error", "BatchSampleSpec", "solve_batched",
 ]
 
 FE_OK, FE_NOT_CONVERGED, FE_DIVERGED = 0, 1, 2
@@ -81,6 +81,17 @@ class FeResult(C.Structure):
 _LIB = None
 
 
+class FeBatchDesc(C.Structure):
+    _fields_ = [("n_samples", C.c_int32), ("grids", C.POINTER(FeGrid)), ("phase", C.POINTER(C.c_void_p)),
+                ("materials", C.POINTER(FeMaterials)), ("macro_strain", C.POINTER(C.c_double)),
+                ("strain", C.POINTER(C.c_void_p))]
+
+
+class FeBatchResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("eta", C.c_double),
+                ("eta_verify_fp64", C.c_double), ("mean_stress", C.c_double * 6)]
+
+
 def load_library():
     """Load libfe.so; raise if it has not been built (no fallback path)."""
     global _LIB
@@ -105,6 +116,9 @@ def load_library():
     lib.fe_effective_stiffness.argtypes = [C.c_void_p, C.c_void_p, FeMaterials, C.c_double,
                                            C.POINTER(C.c_double), C.POINTER(C.c_int32)]
     lib.fe_effective_stiffness.restype = C.c_int
+    lib.fe_solve_batched.argtypes = [C.c_int, C.c_int, C.POINTER(FePlanOptions), C.POINTER(FeBatchDesc), C.c_double,
+                                     C.POINTER(FeBatchResult), C.POINTER(C.c_double)]
+    lib.fe_solve_batched.restype = C.c_int
     lib.fe_status_string.argtypes = [C.c_int]
     lib.fe_status_string.restype = C.c_char_p
     lib.fe_last_error.argtypes = []
@@ -260,3 +274,70 @@ class Plan:
             raise FeError(s, "fe_effective_stiffness")
         del keep
         return np.array(Cv[:]).reshape(6, 6), list(its), s
+
+
+@dataclass
+class BatchSampleSpec:
+    """One sample of a batched solve: a device uint8 phase map (nz, ny, nx),
+    its phases' moduli and the applied macroscopic strain; ``strain`` (optional)
+    is a device tensor (6, nz, ny, nx) of the solve precision receiving eps^n."""
+    phase: object
+    E: object
+    nu: object
+    macro_strain: object
+    strain: object = None
+
+
+def _options(lib, precision, max_iter, ref_rule, ds_beta, E0, nu0, diverge_window, stream):
+    opt = FePlanOptions()
+    lib.fe_plan_options_default(C.byref(opt))
+    opt.precision = PRECISION[precision]
+    opt.max_iter = int(max_iter)
+    opt.ref_rule = REF_RULE[ref_rule]
+    opt.ds_beta = float(ds_beta)
+    opt.E0 = float(E0)
+    opt.nu0 = float(nu0)
+    opt.diverge_window = int(diverge_window)
+    opt.hip_stream = stream
+    return opt
+
+
+def solve_batched(samples, tol, green="R", scheme="AS", precision="fp32", max_iter=1000, ref_rule="paper",
+                  ds_beta=0.5, E0=0.0, nu0=0.25, diverge_window=50, stream=None, raise_on_error=True):
+    """fe_solve_batched over a list of BatchSampleSpec; returns (results, status,
+    seconds) with one Result per sample (eta_history, pass timings empty)."""
+    lib = load_library()
+    n = len(samples)
+    if n == 0:
+        raise ValueError("no samples")
+    grids = (FeGrid * n)()
+    phases = (C.c_void_p * n)()
+    mats = (FeMaterials * n)()
+    macro = (C.c_double * (6 * n))()
+    strains = (C.c_void_p * n)()
+    keep = []
+    for i, sp in enumerate(samples):
+        nz, ny, nx = tuple(sp.phase.shape)
+        grids[i] = FeGrid(nx, ny, nz)
+        phases[i] = _ptr(sp.phase)
+        m, k = _materials(sp.E, sp.nu)
+        keep.append(k)
+        mats[i] = m
+        mv = [float(v) for v in sp.macro_strain]
+        if len(mv) != 6:
+            raise ValueError("macro_strain needs 6 components")
+        for q in range(6):
+            macro[6 * i + q] = mv[q]
+        strains[i] = _ptr(sp.strain)
+    desc = FeBatchDesc(n, grids, phases, mats, macro, strains)
+    opt = _options(lib, precision, max_iter, ref_rule, ds_beta, E0, nu0, diverge_window, stream)
+    res = (FeBatchResult * n)()
+    sec = C.c_double(0.0)
+    s = lib.fe_solve_batched(GREEN[green], SCHEME[scheme], C.byref(opt), C.byref(desc), float(tol), res,
+                             C.byref(sec))
+    if s < 0 and raise_on_error:
+        raise FeError(s, "fe_solve_batched")
+    del keep
+    out = [Result(r.status, r.iterations, r.eta, r.eta_verify_fp64, np.array(r.mean_stress[:]), sec.value)
+           for r in res] if s >= 0 else []
+    return out, s, sec.value

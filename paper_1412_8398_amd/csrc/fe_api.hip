@@ -338,10 +338,10 @@ struct RefMedium {
   double lam0, mu0, kap0;
 };
 
-static RefMedium reference_medium(const fe_plan* p, const fe_materials& m) {
+static RefMedium reference_medium(const fe_plan_options& o, fe_scheme scheme, const fe_materials& m) {
   RefMedium r;
-  if (p->opt.ref_rule == FE_REF_EXPLICIT) {
-    const double E = p->opt.E0, nu = p->opt.nu0;
+  if (o.ref_rule == FE_REF_EXPLICIT) {
+    const double E = o.E0, nu = o.nu0;
     r.lam0 = E * nu / ((1 + nu) * (1 - 2 * nu));
     r.mu0 = E / (2 * (1 + nu));
   } else {
@@ -356,12 +356,12 @@ static RefMedium reference_medium(const fe_plan* p, const fe_materials& m) {
       mmax = std::fmax(mmax, mu);
     }
     double k0, m0;
-    if (p->scheme == FE_ACCELERATED) {  // eq. (17)
+    if (scheme == FE_ACCELERATED) {  // eq. (17)
       k0 = std::sqrt(kmin * kmax);
       m0 = std::sqrt(mmin * mmax);
     } else {  // eq. (18)
-      k0 = p->opt.ds_beta * (kmin + kmax);
-      m0 = p->opt.ds_beta * (mmin + mmax);
+      k0 = o.ds_beta * (kmin + kmax);
+      m0 = o.ds_beta * (mmin + mmax);
     }
     r.mu0 = m0;
     r.lam0 = k0 - 2.0 * m0 / 3.0;
@@ -475,7 +475,7 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
   const WaveTables<T> wt = wave_tables<T>(p);
 
   // per-phase constants (float64 on the host, rounded to T for the kernels)
-  const RefMedium ref = reference_medium(p, mat);
+  const RefMedium ref = reference_medium(p->opt, p->scheme, mat);
   std::vector<PhaseCoef<double>> c64 = phase_coefs(mat, ref);
   std::vector<PhaseCoef<T>> cT(c64.size());
   for (size_t i = 0; i < c64.size(); ++i) {
@@ -786,3 +786,309 @@ extern "C" const char* fe_status_string(fe_status s) {
 }
 
 extern "C" const char* fe_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// batched solves
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+struct BatchClass {
+  Dims d;
+  std::vector<int> ids;  // sample indices of the batch in this class
+  int ncoef = 1;
+  int div_blocks = 0;
+  T* eps = nullptr;
+  T* R = nullptr;
+  cpx<T>* S = nullptr;
+  uint8_t* phase = nullptr;
+  double* partials = nullptr;
+  double* red = nullptr;
+  PhaseCoef<T>* coef = nullptr;
+  PhaseCoef<double>* coef64 = nullptr;
+  GreenConst<T>* gcon = nullptr;
+  int* active = nullptr;
+  int* all = nullptr;
+  cpx<T>* tw[3] = {nullptr, nullptr, nullptr};
+  T* wave[3] = {nullptr, nullptr, nullptr};
+  std::vector<int> act;  // host copy of the active list
+  std::vector<int> rising;
+  std::vector<double> prev;
+  void release() {
+    void* b[] = {eps, R, S, phase, partials, red, coef, coef64, gcon, active, all, tw[0], tw[1], tw[2],
+                 wave[0], wave[1], wave[2]};
+    for (void* x : b)
+      if (x) (void)hipFree(x);
+  }
+};
+
+template <typename T>
+fe_status alloc_class(BatchClass<T>& c, int op) {
+  const size_t n = c.ids.size();
+  const long long N = c.d.N;
+  const size_t spec = (size_t)c.d.H * c.d.ny * c.d.nx;
+  HIP_TRY(hipMalloc((void**)&c.eps, n * 6 * N * sizeof(T)));
+  HIP_TRY(hipMalloc((void**)&c.R, n * 3 * N * sizeof(T)));
+  HIP_TRY(hipMalloc((void**)&c.S, n * 3 * spec * sizeof(cpx<T>)));
+  HIP_TRY(hipMalloc((void**)&c.phase, n * N));
+  HIP_TRY(hipMalloc((void**)&c.partials, n * (size_t)c.div_blocks * 7 * sizeof(double)));
+  HIP_TRY(hipMalloc((void**)&c.red, n * 8 * sizeof(double)));
+  HIP_TRY(hipMalloc((void**)&c.coef, n * c.ncoef * sizeof(PhaseCoef<T>)));
+  HIP_TRY(hipMalloc((void**)&c.coef64, n * c.ncoef * sizeof(PhaseCoef<double>)));
+  HIP_TRY(hipMalloc((void**)&c.gcon, n * sizeof(GreenConst<T>)));
+  HIP_TRY(hipMalloc((void**)&c.active, n * sizeof(int)));
+  HIP_TRY(hipMalloc((void**)&c.all, n * sizeof(int)));
+  const int dims[3] = {c.d.nx, c.d.ny, c.d.nz};
+  for (int a = 0; a < 3; ++a) {
+    std::vector<double> tw = twiddles(dims[a]), wv = wave_table(dims[a], op);
+    std::vector<T> twt(tw.begin(), tw.end()), wvt(wv.begin(), wv.end());
+    HIP_TRY(hipMalloc((void**)&c.tw[a], twt.size() * sizeof(T)));
+    HIP_TRY(hipMalloc((void**)&c.wave[a], wvt.size() * sizeof(T)));
+    HIP_TRY(hipMemcpy(c.tw[a], twt.data(), twt.size() * sizeof(T), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c.wave[a], wvt.data(), wvt.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+  return FE_OK;
+}
+
+template <typename T>
+fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const fe_batch_desc* desc, double tol,
+                             fe_batch_result* results, double* seconds) {
+  hipStream_t s = (hipStream_t)o.hip_stream;
+  const int ns = desc->n_samples;
+  // group samples by grid
+  std::vector<BatchClass<T>> cls;
+  for (int i = 0; i < ns; ++i) {
+    const fe_grid& g = desc->grids[i];
+    size_t c = 0;
+    for (; c < cls.size(); ++c)
+      if (cls[c].d.nx == g.nx && cls[c].d.ny == g.ny && cls[c].d.nz == g.nz) break;
+    if (c == cls.size()) {
+      BatchClass<T> bc;
+      bc.d = Dims{g.nx, g.ny, g.nz, g.nz / 2 + 1, (long long)g.nx * g.ny * g.nz};
+      cls.push_back(bc);
+    }
+    cls[c].ids.push_back(i);
+    cls[c].ncoef = std::max(cls[c].ncoef, desc->materials[i].n_phases);
+  }
+  struct Guard {
+    std::vector<BatchClass<T>>& v;
+    ~Guard() {
+      for (auto& c : v) c.release();
+    }
+  } guard{cls};
+
+  int* hflag = nullptr;
+  HIP_TRY(hipMalloc((void**)&hflag, sizeof(int)));
+  struct FlagGuard {
+    int* f;
+    ~FlagGuard() { (void)hipFree(f); }
+  } fg{hflag};
+  HIP_TRY(hipMemsetAsync(hflag, 0, sizeof(int), s));
+
+  for (auto& c : cls) {
+    const long long N = c.d.N;
+    c.div_blocks = div_partial_count(c.d);
+    fe_status st = alloc_class(c, op);
+    if (st != FE_OK) return st;
+    const size_t n = c.ids.size();
+    std::vector<PhaseCoef<T>> cT(n * c.ncoef);
+    std::vector<PhaseCoef<double>> c64(n * c.ncoef);
+    std::vector<GreenConst<T>> gv(n);
+    std::vector<int> idx(n);
+    for (size_t j = 0; j < n; ++j) {
+      const int i = c.ids[j];
+      idx[j] = (int)j;
+      const fe_materials& m = desc->materials[i];
+      const RefMedium ref = reference_medium(o, accel ? FE_ACCELERATED : FE_DIRECT, m);
+      std::vector<PhaseCoef<double>> pc = phase_coefs(m, ref);
+      for (int q = 0; q < m.n_phases; ++q) {
+        c64[j * c.ncoef + q] = pc[q];
+        PhaseCoef<T>& t = cT[j * c.ncoef + q];
+        t.lam = T(pc[q].lam);
+        t.mu = T(pc[q].mu);
+        t.dlam = T(pc[q].dlam);
+        t.dmu = T(pc[q].dmu);
+        t.ak = T(pc[q].ak);
+        t.am = T(pc[q].am);
+        t.pad0 = t.pad1 = T(0);
+      }
+      GreenConst<T>& g = gv[j];
+      g.lam0 = T(ref.lam0);
+      g.mu0 = T(ref.mu0);
+      g.cr = T((ref.lam0 + ref.mu0) / (ref.lam0 + 2.0 * ref.mu0));
+      g.s1 = T(1.0 / (2.0 * ref.mu0));
+      g.s2 = T(ref.lam0 / (2.0 * ref.mu0 * (3.0 * ref.lam0 + 2.0 * ref.mu0)));
+      g.inv_n = T(1.0 / (double)N);
+      for (int q = 0; q < 6; ++q) g.macro[q] = T(desc->macro_strain[6 * i + q]);
+      HIP_TRY(hipMemcpyAsync(c.phase + j * N, desc->phase[i], N, hipMemcpyDeviceToDevice, s));
+      Launch<T>::check_phase(c.phase + j * N, N, m.n_phases, hflag, s);
+      Launch<T>::fill_macro(c.eps + j * 6 * N, N, desc->macro_strain + 6 * i, s);
+    }
+    HIP_TRY(hipMemcpyAsync(c.coef, cT.data(), cT.size() * sizeof(PhaseCoef<T>), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c.coef64, c64.data(), c64.size() * sizeof(PhaseCoef<double>), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c.gcon, gv.data(), n * sizeof(GreenConst<T>), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c.all, idx.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c.active, idx.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    c.act = idx;
+    c.rising.assign(n, 0);
+    c.prev.assign(n, INFINITY);
+  }
+  int flag = 0;
+  HIP_TRY(hipMemcpy(&flag, hflag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) return fail(FE_ERR_INVALID_ARG, "a phase map holds a label >= its n_phases");
+
+  for (int i = 0; i < ns; ++i) {
+    results[i].status = FE_NOT_CONVERGED;
+    results[i].iterations = 0;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, s));
+  std::vector<double> hred;
+  for (int k = 0;; ++k) {
+    bool any = false;
+    for (auto& c : cls) {
+      const int na = (int)c.act.size();
+      if (!na) continue;
+      any = true;
+      const Batch bt{c.active, c.ncoef};
+      Launch<T>::div(c.eps, c.phase, c.coef, c.R, nullptr, c.partials, c.d, op, s, bt, na);
+      launch_reduce(c.partials, c.div_blocks, 7, c.red, s, c.active, na);
+    }
+    if (!any) break;
+    HIP_TRY(hipStreamSynchronize(s));
+    bool left = false;
+    for (auto& c : cls) {
+      if (c.act.empty()) continue;
+      hred.resize(c.ids.size() * 8);
+      HIP_TRY(hipMemcpy(hred.data(), c.red, hred.size() * sizeof(double), hipMemcpyDeviceToHost));
+      std::vector<int> keep;
+      for (int j : c.act) {
+        const double* r = &hred[8 * j];
+        double mean[6];
+        for (int q = 0; q < 6; ++q) mean[q] = r[1 + q] / (double)c.d.N;
+        const double eta = std::sqrt(r[0] / (double)c.d.N) / frob(mean);
+        fe_batch_result& out = results[c.ids[j]];
+        out.iterations = k;
+        out.eta = eta;
+        for (int q = 0; q < 6; ++q) out.mean_stress[q] = mean[q];
+        // same stopping order as the single-sample solve
+        if (!std::isfinite(eta)) {
+          out.status = FE_DIVERGED;
+          continue;
+        }
+        if (eta <= tol) {
+          out.status = FE_OK;
+          continue;
+        }
+        if (k >= o.max_iter) {
+          out.status = FE_NOT_CONVERGED;
+          continue;
+        }
+        c.rising[j] = eta > c.prev[j] ? c.rising[j] + 1 : 0;
+        c.prev[j] = eta;
+        if (o.diverge_window > 0 && c.rising[j] >= o.diverge_window) {
+          out.status = FE_DIVERGED;
+          continue;
+        }
+        keep.push_back(j);
+      }
+      c.act.swap(keep);  // c.act stays untouched until the next synchronisation
+      if (!c.act.empty()) {
+        left = true;
+        HIP_TRY(hipMemcpyAsync(c.active, c.act.data(), c.act.size() * sizeof(int), hipMemcpyHostToDevice, s));
+      }
+    }
+    if (!left) break;
+    for (auto& c : cls) {
+      const int na = (int)c.act.size();
+      if (!na) continue;
+      const Batch bt{c.active, c.ncoef};
+      const WaveTables<T> wt{c.wave[0], c.wave[1], c.wave[2]};
+      GreenConst<T> g0;
+      std::memset(&g0, 0, sizeof g0);
+      Launch<T>::zr2c(c.R, c.S, 3, c.d, c.tw[2], s, bt, na);
+      Launch<T>::yfft(c.S, 3, c.d, c.tw[1], 0, s, bt, na);
+      Launch<T>::xgreen3(c.S, c.d, c.tw[0], wt, g0, op, s, bt, c.gcon, na);
+      Launch<T>::yfft(c.S, 3, c.d, c.tw[1], 1, s, bt, na);
+      Launch<T>::zc2r(c.S, c.R, 3, c.d, c.tw[2], s, bt, na);
+      Launch<T>::grad_update(c.R, c.eps, c.phase, c.coef, g0, nullptr, c.d, op, accel, s, bt, c.gcon, na);
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipEventRecord(e1, s));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (seconds) *seconds = ms * 1e-3;
+
+  // float64 verification and outputs
+  for (auto& c : cls) {
+    const int n = (int)c.ids.size();
+    const Batch bt{c.all, c.ncoef};
+    launch_div64<T>(c.eps, c.phase, c.coef64, nullptr, nullptr, c.partials, c.d, op, s, bt, n);
+    launch_reduce(c.partials, c.div_blocks, 7, c.red, s, c.all, n);
+    hred.resize((size_t)n * 8);
+    HIP_TRY(hipMemcpyAsync(hred.data(), c.red, hred.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int j = 0; j < n; ++j) {
+      const double* r = &hred[8 * j];
+      double mean[6];
+      for (int q = 0; q < 6; ++q) mean[q] = r[1 + q] / (double)c.d.N;
+      results[c.ids[j]].eta_verify_fp64 = std::sqrt(r[0] / (double)c.d.N) / frob(mean);
+      if (desc->strain && desc->strain[c.ids[j]])
+        HIP_TRY(hipMemcpyAsync(desc->strain[c.ids[j]], c.eps + (size_t)j * 6 * c.d.N, 6 * c.d.N * sizeof(T),
+                               hipMemcpyDeviceToDevice, s));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  fe_status worst = FE_OK;
+  for (int i = 0; i < ns; ++i)
+    if (results[i].status > worst) worst = (fe_status)results[i].status;
+  return worst;
+}
+
+}  // namespace
+
+extern "C" fe_status fe_solve_batched(fe_discretization disc, fe_scheme scheme, const fe_plan_options* opt,
+                                      const fe_batch_desc* desc, double tol, fe_batch_result* results,
+                                      double* seconds) {
+  if (!desc || !results) return fail(FE_ERR_INVALID_ARG, "desc or results is NULL");
+  if (disc != FE_GREEN_WP && disc != FE_GREEN_ROT)
+    return fail(disc == FE_GREEN_MS ? FE_ERR_UNSUPPORTED : FE_ERR_INVALID_ARG,
+                "batched solves support the WP and ROT operators");
+  if (scheme != FE_DIRECT && scheme != FE_ACCELERATED) return fail(FE_ERR_INVALID_ARG, "unknown scheme");
+  fe_plan_options o;
+  fe_plan_options_default(&o);
+  if (opt) {
+    if (opt->struct_size != sizeof(fe_plan_options)) return fail(FE_ERR_INVALID_ARG, "bad fe_plan_options.struct_size");
+    o = *opt;
+  }
+  if (o.precision != FE_FP32 && o.precision != FE_FP64) return fail(FE_ERR_INVALID_ARG, "unknown precision");
+  if (o.max_iter < 0) return fail(FE_ERR_INVALID_ARG, "max_iter must be >= 0");
+  if (o.ref_rule == FE_REF_EXPLICIT &&
+      !(std::isfinite(o.E0) && o.E0 > 0.0 && std::isfinite(o.nu0) && o.nu0 > -1.0 && o.nu0 < 0.5))
+    return fail(FE_ERR_INVALID_ARG, "explicit reference needs E0 > 0 and -1 < nu0 < 0.5");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FE_ERR_INVALID_ARG, "tol must be finite and > 0");
+  if (desc->n_samples < 1 || desc->n_samples > 65535) return fail(FE_ERR_INVALID_ARG, "n_samples must be in [1, 65535]");
+  if (!desc->grids || !desc->phase || !desc->materials || !desc->macro_strain)
+    return fail(FE_ERR_INVALID_ARG, "desc arrays are NULL");
+  for (int i = 0; i < desc->n_samples; ++i) {
+    const fe_grid& g = desc->grids[i];
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a)
+      if (!supported_length(n[a])) return fail(FE_ERR_UNSUPPORTED, "sample %d: grid dimension %d = %d", i, a, n[a]);
+    if (!desc->phase[i]) return fail(FE_ERR_INVALID_ARG, "sample %d: phase is NULL", i);
+    fe_status st = validate_materials(desc->materials[i]);
+    if (st != FE_OK) return st;
+    for (int q = 0; q < 6; ++q)
+      if (!std::isfinite(desc->macro_strain[6 * i + q])) return fail(FE_ERR_INVALID_ARG, "sample %d: macro strain", i);
+  }
+  const int op = disc == FE_GREEN_WP ? OP_WP : OP_ROT;
+  if (o.precision == FE_FP64) return solve_batched_impl<double>(op, scheme == FE_ACCELERATED, o, desc, tol, results, seconds);
+  return solve_batched_impl<float>(op, scheme == FE_ACCELERATED, o, desc, tol, results, seconds);
+}

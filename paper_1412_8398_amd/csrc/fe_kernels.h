@@ -34,6 +34,15 @@ struct GreenConst {
   T macro[6]; // eps_bar (tensor Voigt order)
 };
 
+// Batched launches: blockIdx.y selects a slot of the active-sample list; every
+// per-sample buffer of a size class is packed with a fixed stride (strain 6N,
+// phase N, real work planes ncomp*N, half spectra ncomp*H*ny*nx, partial sums
+// gridDim.x*7, phase constants ncoef).
+struct Batch {
+  const int* active;  // null: a single sample (sample 0)
+  int ncoef;          // PhaseCoef entries per sample
+};
+
 // Per-axis wave tables, 2 reals per index m in [0, n):
 //   ROT: (sin(pi m'/n), cos(pi m'/n));  WP: (cos q - 1, sin q);  MS: (q, 1 if Nyquist else 0)
 template <typename T>
@@ -55,13 +64,15 @@ struct Launch {
   // divergence of sigma before eta's reduction.  Returns the number of partial
   // sums (7 doubles each) written.
   static int div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, const T* Dsig_base,
-                 double* partials, Dims d, int op, hipStream_t s);
-  // rfield (nullable, 6 planes) replaces the constant applied strain.
+                 double* partials, Dims d, int op, hipStream_t s, Batch bt = Batch{nullptr, 0}, int nsamp = 1);
+  // rfield (nullable, 6 planes) replaces the constant applied strain; gs
+  // (nullable) holds per-sample constants that replace g.
   static void grad_update(const T* U, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef,
-                          GreenConst<T> g, const T* rfield, Dims d, int op, int accelerated, hipStream_t s);
+                          GreenConst<T> g, const T* rfield, Dims d, int op, int accelerated, hipStream_t s,
+                          Batch bt = Batch{nullptr, 0}, const GreenConst<T>* gs = nullptr, int nsamp = 1);
   static void axpy(T* y, const T* x, long long n, hipStream_t s);  // y += x
   static void xgreen3(cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> wt, GreenConst<T> g, int op,
-                      hipStream_t s);
+                      hipStream_t s, Batch bt = Batch{nullptr, 0}, const GreenConst<T>* gs = nullptr, int nsamp = 1);
 
   // Six-component form (every operator).
   static void tau6(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* out, int write_sigma,
@@ -75,9 +86,12 @@ struct Launch {
                       int accelerated, hipStream_t s);
 
   // Strided FFT passes.
-  static void zr2c(const T* R, cpx<T>* S, int ncomp, Dims d, const cpx<T>* twz, hipStream_t s);
-  static void zc2r(const cpx<T>* S, T* R, int ncomp, Dims d, const cpx<T>* twz, hipStream_t s);
-  static void yfft(cpx<T>* S, int ncomp, Dims d, const cpx<T>* twy, int inverse, hipStream_t s);
+  static void zr2c(const T* R, cpx<T>* S, int ncomp, Dims d, const cpx<T>* twz, hipStream_t s,
+                   Batch bt = Batch{nullptr, 0}, int nsamp = 1);
+  static void zc2r(const cpx<T>* S, T* R, int ncomp, Dims d, const cpx<T>* twz, hipStream_t s,
+                   Batch bt = Batch{nullptr, 0}, int nsamp = 1);
+  static void yfft(cpx<T>* S, int ncomp, Dims d, const cpx<T>* twy, int inverse, hipStream_t s,
+                   Batch bt = Batch{nullptr, 0}, int nsamp = 1);
 
   static void stress(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* sigma, long long N,
                      hipStream_t s);
@@ -93,13 +107,19 @@ int launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<doubl
 // (storage type, nullable); partial sums as in Launch::div.
 template <typename TS>
 int launch_div64(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* Dtau, TS* Dsig,
-                 double* partials, Dims d, int op, hipStream_t s);
+                 double* partials, Dims d, int op, hipStream_t s, Batch bt = Batch{nullptr, 0}, int nsamp = 1);
 
 // r = eps_bar + sym grad_h U - eps in float64 arithmetic (U float64).
 template <typename TE>
 void launch_residual(const double* U, const TE* eps, GreenConst<double> g, TE* r, Dims d, int op, hipStream_t s);
 
-void launch_reduce(const double* partials, int nblocks, int nv, double* out, hipStream_t s);
+// Number of partial sums (per sample) a divergence launch over grid d writes.
+int div_partial_count(Dims d);
+
+// Fixed-order sums of per-block partials: out[8*sample + i] for i < nv; with an
+// active list, one reduction per active sample (partials strided by nblocks*nv).
+void launch_reduce(const double* partials, int nblocks, int nv, double* out, hipStream_t s,
+                   const int* active = nullptr, int nsamp = 1);
 
 constexpr int kThreads = 256;
 constexpr int kMaxReduceBlocks = 4096;

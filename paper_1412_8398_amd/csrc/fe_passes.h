@@ -50,8 +50,9 @@ struct alignas(4 * sizeof(T)) cpx2 {
 // ---------------------------------------------------------------------------
 template <typename T, int N, bool INV>
 __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_ypass(cpx<T>* __restrict__ S, Dims d,
-                                                                const cpx<T>* __restrict__ tw) {
+                                                                const cpx<T>* __restrict__ tw, Batch bt) {
   using C = StridedCfg<T, N>;
+  if (bt.active) S += (long long)bt.active[blockIdx.y] * (gridDim.x / (((d.nx + C::TX - 1) / C::TX) * d.H)) * d.H * d.ny * d.nx;
   __shared__ cpx<T> lds[N * C::TX];
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
   const int ntx = (d.nx + C::TX - 1) / C::TX;
@@ -79,8 +80,14 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_ypass(cpx<T>* __rest
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __restrict__ R, cpx<T>* __restrict__ S,
-                                                               Dims d, const cpx<T>* __restrict__ tw) {
+                                                               Dims d, const cpx<T>* __restrict__ tw, Batch bt) {
   using C = StridedCfg<T, N>;
+  if (bt.active) {
+    const long long nc = gridDim.x / (((d.nx / 2 + C::TX - 1) / C::TX) * d.ny);
+    const long long smp = bt.active[blockIdx.y];
+    R += smp * nc * d.N;
+    S += smp * nc * d.H * d.ny * d.nx;
+  }
   __shared__ cpx<T> lds[N * C::TX];
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
   const int npair = d.nx / 2;
@@ -117,8 +124,14 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __rest
 // Z(nz-m) = conj A(m) + i conj B(m); the inverse transform of Z is a + i b.
 template <typename T, int N>
 __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* __restrict__ S, T* __restrict__ R,
-                                                               Dims d, const cpx<T>* __restrict__ tw) {
+                                                               Dims d, const cpx<T>* __restrict__ tw, Batch bt) {
   using C = StridedCfg<T, N>;
+  if (bt.active) {
+    const long long nc = gridDim.x / (((d.nx / 2 + C::TX - 1) / C::TX) * d.ny);
+    const long long smp = bt.active[blockIdx.y];
+    R += smp * nc * d.N;
+    S += smp * nc * d.H * d.ny * d.nx;
+  }
   __shared__ cpx<T> lds[N * C::TX];
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
   const int npair = d.nx / 2;
@@ -163,8 +176,14 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* _
 template <typename T, int N, int OP>
 __global__ __launch_bounds__((LineCfg<T, N, 3>::NT)) void k_xgreen3(cpx<T>* __restrict__ S, Dims d,
                                                                   const cpx<T>* __restrict__ tw, WaveTables<T> wt,
-                                                                  GreenConst<T> g) {
+                                                                  GreenConst<T> g, Batch bt,
+                                                                  const GreenConst<T>* __restrict__ gs) {
   using C = LineCfg<T, N, 3>;
+  if (bt.active) {
+    const long long smp = bt.active[blockIdx.y];
+    S += smp * 3 * d.H * d.ny * d.nx;
+    if (gs) g = gs[smp];
+  }
   __shared__ cpx<T> lds[C::LPB * C::LINE];
   const int t = threadIdx.x % C::P, l = threadIdx.x / C::P;
   const int nlines = d.H * d.ny;

@@ -102,7 +102,17 @@ template <typename TS, typename TC, typename TD, int OP>
 __global__ __launch_bounds__(DX * DY) void k_div(const TS* __restrict__ eps, const uint8_t* __restrict__ phase,
                                                  const PhaseCoef<TC>* __restrict__ coef, TD* __restrict__ Dtau,
                                                  TS* __restrict__ Dsig, const TS* __restrict__ Dsig_base,
-                                                 double* __restrict__ partials, Dims d, int zchunk) {
+                                                 double* __restrict__ partials, Dims d, int zchunk, Batch bt) {
+  {
+    const long long smp = bt.active ? bt.active[blockIdx.y] : 0;
+    eps += smp * 6 * d.N;
+    phase += smp * d.N;
+    coef += smp * bt.ncoef;
+    if (Dtau) Dtau += smp * 3 * d.N;
+    if (Dsig) Dsig += smp * 3 * d.N;
+    if (Dsig_base) Dsig_base += smp * 3 * d.N;
+    partials += smp * gridDim.x * 7;
+  }
   __shared__ TC st[DY + 1][DX + 1][6];
   __shared__ TC ss[DY + 1][DX + 1][6];
   __shared__ double red[7 * 16];
@@ -226,6 +236,8 @@ static DivGrid div_grid(const Dims& d) {
   return DivGrid{bxy * nch, zchunk};
 }
 
+int div_partial_count(Dims d) { return div_grid(d).blocks; }
+
 // --------------------------------------------------------------------------
 // strain update from the displacement U (WP, ROT)
 // ROT: grad at voxel v from its corners v + a: d_i U_j = 1/4 sum_a s_i(a) U_j(v+a),
@@ -242,8 +254,18 @@ template <typename T, int OP, bool AS>
 __global__ __launch_bounds__(256) void k_grad_update(const T* __restrict__ U, T* __restrict__ eps,
                                                      const uint8_t* __restrict__ phase,
                                                      const PhaseCoef<T>* __restrict__ coef, GreenConst<T> g,
-                                                     const T* __restrict__ rfield, Dims d) {
+                                                     const T* __restrict__ rfield, Dims d, Batch bt,
+                                                     const GreenConst<T>* __restrict__ gs) {
   const long long N = d.N;
+  {
+    const long long smp = bt.active ? bt.active[blockIdx.y] : 0;
+    U += smp * 3 * N;
+    eps += smp * 6 * N;
+    phase += smp * N;
+    coef += smp * bt.ncoef;
+    if (rfield) rfield += smp * 6 * N;
+    if (gs) g = gs[smp];
+  }
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
     const int x = (int)(v % nx);
@@ -446,8 +468,11 @@ __global__ __launch_bounds__(256) void k_stress(const T* __restrict__ eps, const
 // final reduction: fixed-order sum of per-block partials (deterministic)
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int nblocks, int nv,
-                                                double* __restrict__ out) {
+                                                double* __restrict__ out, const int* __restrict__ active) {
   __shared__ double red[8 * 16];
+  const long long smp = active ? active[blockIdx.x] : 0;
+  partials += smp * (long long)nblocks * nv;
+  out += smp * 8;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
     for (int i = 0; i < nv && i < 8; ++i) acc[i] += partials[(long long)b * nv + i];
@@ -483,14 +508,15 @@ void Launch<T>::check_phase(const uint8_t* phase, long long N, int n_phases, int
 
 template <typename T>
 int Launch<T>::div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, const T* Dsig_base,
-                   double* partials, Dims d, int op, hipStream_t s) {
+                   double* partials, Dims d, int op, hipStream_t s, Batch bt, int nsamp) {
   const DivGrid gd = div_grid(d);
+  const dim3 grid(gd.blocks, nsamp);
   if (op == OP_ROT)
-    hipLaunchKernelGGL((k_div<T, T, T, OP_ROT>), dim3(gd.blocks), dim3(DX * DY), 0, s, eps, phase, coef, D,
-                       (T*)nullptr, Dsig_base, partials, d, gd.zchunk);
+    hipLaunchKernelGGL((k_div<T, T, T, OP_ROT>), grid, dim3(DX * DY), 0, s, eps, phase, coef, D, (T*)nullptr,
+                       Dsig_base, partials, d, gd.zchunk, bt);
   else
-    hipLaunchKernelGGL((k_div<T, T, T, OP_WP>), dim3(gd.blocks), dim3(DX * DY), 0, s, eps, phase, coef, D,
-                       (T*)nullptr, Dsig_base, partials, d, gd.zchunk);
+    hipLaunchKernelGGL((k_div<T, T, T, OP_WP>), grid, dim3(DX * DY), 0, s, eps, phase, coef, D, (T*)nullptr,
+                       Dsig_base, partials, d, gd.zchunk, bt);
   return gd.blocks;
 }
 
@@ -502,31 +528,33 @@ int launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<doubl
 
 template <typename TS>
 int launch_div64(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* Dtau, TS* Dsig,
-                 double* partials, Dims d, int op, hipStream_t s) {
+                 double* partials, Dims d, int op, hipStream_t s, Batch bt, int nsamp) {
   const DivGrid gd = div_grid(d);
+  const dim3 grid(gd.blocks, nsamp);
   if (op == OP_ROT)
-    hipLaunchKernelGGL((k_div<TS, double, double, OP_ROT>), dim3(gd.blocks), dim3(DX * DY), 0, s, eps, phase, coef,
-                       Dtau, Dsig, (const TS*)nullptr, partials, d, gd.zchunk);
+    hipLaunchKernelGGL((k_div<TS, double, double, OP_ROT>), grid, dim3(DX * DY), 0, s, eps, phase, coef, Dtau, Dsig,
+                       (const TS*)nullptr, partials, d, gd.zchunk, bt);
   else
-    hipLaunchKernelGGL((k_div<TS, double, double, OP_WP>), dim3(gd.blocks), dim3(DX * DY), 0, s, eps, phase, coef,
-                       Dtau, Dsig, (const TS*)nullptr, partials, d, gd.zchunk);
+    hipLaunchKernelGGL((k_div<TS, double, double, OP_WP>), grid, dim3(DX * DY), 0, s, eps, phase, coef, Dtau, Dsig,
+                       (const TS*)nullptr, partials, d, gd.zchunk, bt);
   return gd.blocks;
 }
 
 template <typename T>
 void Launch<T>::grad_update(const T* U, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, GreenConst<T> g,
-                            const T* rfield, Dims d, int op, int accelerated, hipStream_t s) {
-  const dim3 gr(grid_for(d.N, 1 << 20)), bl(kThreads);
+                            const T* rfield, Dims d, int op, int accelerated, hipStream_t s, Batch bt,
+                            const GreenConst<T>* gs, int nsamp) {
+  const dim3 gr(grid_for(d.N, 1 << 20), nsamp), bl(kThreads);
   if (op == OP_ROT) {
     if (accelerated)
-      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, true>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d);
+      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, true>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d, bt, gs);
     else
-      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, false>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d);
+      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, false>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d, bt, gs);
   } else {
     if (accelerated)
-      hipLaunchKernelGGL((k_grad_update<T, OP_WP, true>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d);
+      hipLaunchKernelGGL((k_grad_update<T, OP_WP, true>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d, bt, gs);
     else
-      hipLaunchKernelGGL((k_grad_update<T, OP_WP, false>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d);
+      hipLaunchKernelGGL((k_grad_update<T, OP_WP, false>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d, bt, gs);
   }
 }
 
@@ -568,8 +596,9 @@ void Launch<T>::stress(const T* eps, const uint8_t* phase, const PhaseCoef<T>* c
   hipLaunchKernelGGL((k_stress<T>), dim3(grid_for(N, 1 << 20)), dim3(kThreads), 0, s, eps, phase, coef, sigma, N);
 }
 
-void launch_reduce(const double* partials, int nblocks, int nv, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nblocks, nv, out);
+void launch_reduce(const double* partials, int nblocks, int nv, double* out, hipStream_t s, const int* active,
+                   int nsamp) {
+  hipLaunchKernelGGL(k_reduce, dim3(nsamp), dim3(256), 0, s, partials, nblocks, nv, out, active);
 }
 
 #define FE_INSTANTIATE(T)                                                                                 \
@@ -577,10 +606,11 @@ void launch_reduce(const double* partials, int nblocks, int nv, double* out, hip
   template void Launch<T>::convert_to(T*, const void*, int, long long, hipStream_t);                     \
   template void Launch<T>::check_phase(const uint8_t*, long long, int, int*, hipStream_t);               \
   template int Launch<T>::div(const T*, const uint8_t*, const PhaseCoef<T>*, T*, const T*, double*, Dims, int, \
-                              hipStream_t);                                                               \
+                              hipStream_t, Batch, int);                                                   \
   template void Launch<T>::axpy(T*, const T*, long long, hipStream_t);                                     \
   template void Launch<T>::grad_update(const T*, T*, const uint8_t*, const PhaseCoef<T>*, GreenConst<T>,  \
-                                       const T*, Dims, int, int, hipStream_t);                            \
+                                       const T*, Dims, int, int, hipStream_t, Batch, const GreenConst<T>*, \
+                                       int);                                                              \
   template void Launch<T>::tau6(const T*, const uint8_t*, const PhaseCoef<T>*, T*, int, double*, int, Dims, \
                                 hipStream_t);                                                             \
   template void Launch<T>::update6(const T*, T*, const uint8_t*, const PhaseCoef<T>*, Dims, int, hipStream_t); \
@@ -593,9 +623,9 @@ template int launch_verify_div<float>(const float*, const uint8_t*, const PhaseC
 template int launch_verify_div<double>(const double*, const uint8_t*, const PhaseCoef<double>*, double*, Dims, int,
                                        hipStream_t);
 template int launch_div64<float>(const float*, const uint8_t*, const PhaseCoef<double>*, double*, float*, double*,
-                                 Dims, int, hipStream_t);
+                                 Dims, int, hipStream_t, Batch, int);
 template int launch_div64<double>(const double*, const uint8_t*, const PhaseCoef<double>*, double*, double*, double*,
-                                  Dims, int, hipStream_t);
+                                  Dims, int, hipStream_t, Batch, int);
 template void launch_residual<float>(const double*, const float*, GreenConst<double>, float*, Dims, int, hipStream_t);
 template void launch_residual<double>(const double*, const double*, GreenConst<double>, double*, Dims, int,
                                       hipStream_t);

@@ -91,3 +91,35 @@ def test_solve_rejects_null_plan_and_bad_arguments(lib):
     r = fe.FeResult()
     assert lib.fe_solve(None, None, m, macro, 1e-6, None, C.byref(r)) == fe.FE_ERR_INVALID_ARG
     assert lib.fe_effective_stiffness(None, None, m, 1e-6, None, None) == fe.FE_ERR_INVALID_ARG
+
+
+def _batch_desc(dims, n_phases=2):
+    grids = (fe.FeGrid * 1)(fe.FeGrid(*dims))
+    phase = (C.c_void_p * 1)(0x1000)  # never dereferenced: arguments fail first
+    E = (C.c_double * n_phases)(*[1.0 + i for i in range(n_phases)])
+    nu = (C.c_double * n_phases)(*[0.3] * n_phases)
+    mats = (fe.FeMaterials * 1)(fe.FeMaterials(n_phases, E, nu))
+    macro = (C.c_double * 6)(1, 0, 0, 0, 0, 0)
+    desc = fe.FeBatchDesc(1, grids, phase, mats, macro, None)
+    return desc, (grids, phase, E, nu, mats, macro)
+
+
+def test_batched_solve_rejects_bad_arguments_before_device_work(lib):
+    res = (fe.FeBatchResult * 1)()
+    desc, keep = _batch_desc((16, 16, 16))
+    call = lambda disc, scheme, d, tol: lib.fe_solve_batched(disc, scheme, None, d, tol, res, None)  # noqa: E731
+    assert call(2, 1, None, 1e-6) == fe.FE_ERR_INVALID_ARG
+    assert call(0, 1, C.byref(desc), 1e-6) == fe.FE_ERR_UNSUPPORTED  # MS: six-component form only
+    assert "WP and ROT" in fe.last_error()
+    assert call(7, 1, C.byref(desc), 1e-6) == fe.FE_ERR_INVALID_ARG
+    assert call(2, 3, C.byref(desc), 1e-6) == fe.FE_ERR_INVALID_ARG
+    assert call(2, 1, C.byref(desc), 0.0) == fe.FE_ERR_INVALID_ARG
+    bad, keep2 = _batch_desc((16, 36, 16))
+    assert call(2, 1, C.byref(bad), 1e-6) == fe.FE_ERR_UNSUPPORTED
+    assert "grid dimension" in fe.last_error()
+    empty, keep3 = _batch_desc((16, 16, 16))
+    empty.n_samples = 0
+    assert call(1, 0, C.byref(empty), 1e-6) == fe.FE_ERR_INVALID_ARG
+    nomat, keep4 = _batch_desc((16, 16, 16))
+    keep4[4][0].E[0] = -1.0
+    assert call(1, 0, C.byref(nomat), 1e-6) == fe.FE_ERR_INVALID_ARG

@@ -1,0 +1,134 @@
+"""Batched solves of uneven samples (fe_solve_batched).
+
+Each sample of a batch must follow exactly the iteration a single-sample
+fe_solve of the same plan options performs (same kernels, same constants,
+same fixed-order reductions): iteration counts, eta and the strain field are
+compared bit for bit against single solves with refinement off.  One float64
+sample is also compared with the oracle at its converged iteration count
+(relative L2 <= 1e-12, the single-solve float64 bar).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from microstructure import boolean_spheres, laminate, sphere_inclusion
+
+torch = pytest.importorskip("torch")
+import paper_1412_8398_amd as fe  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _samples():
+    """Four samples over three grid classes, two contrasts, two phase counts."""
+    a, _ = boolean_spheres((32, 32, 32), 3.0, 0.2, 11)
+    b, _ = boolean_spheres((24, 32, 48), 3.0, 0.3, 12)  # (nz, ny, nx)
+    c, _ = boolean_spheres((32, 32, 32), 4.0, 0.15, 13)
+    d = laminate((16, 16, 16), [0] * 4 + [1] * 8 + [2] * 4)  # three layers along x
+    d[sphere_inclusion((16, 16, 16), (8, 8, 8), 3.0) == 1] = 3   # and a fourth phase
+    n_d = 4
+    specs = [
+        (a, [1.0, 10.0], [0.3, 0.3], [0, 0, 0, 0, 0, 1.0]),
+        (b, [1.0, 10.0], [0.3, 0.25], [0.5, -0.2, 0.1, 0.0, 0.3, 0.0]),
+        (c, [1.0, 100.0], [0.2, 0.35], [1.0, 0, 0, 0, 0, 0]),
+        (d, list(np.linspace(1.0, 20.0, n_d)), [0.3] * n_d, [0.2, 0.2, -0.1, 0.4, 0.0, 0.1]),
+    ]
+    return specs
+
+
+def _single(phase, E, nu, macro, op, scheme, precision, tol, max_iter):
+    nz, ny, nx = phase.shape
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    with fe.Plan((nx, ny, nz), green=op, scheme=scheme, precision=precision, max_iter=max_iter,
+                 refine=False) as plan:
+        eps = torch.empty((6, nz, ny, nx), dtype=dt, device="cuda")
+        r = plan.solve(_dev(phase), E, nu, macro, tol, strain=eps, raise_on_error=False)
+        torch.cuda.synchronize()
+    return r, eps.cpu().numpy()
+
+
+def _batched(specs, op, scheme, precision, tol, max_iter):
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    samples, outs = [], []
+    for ph, E, nu, macro in specs:
+        nz, ny, nx = ph.shape
+        eps = torch.empty((6, nz, ny, nx), dtype=dt, device="cuda")
+        outs.append(eps)
+        samples.append(fe.BatchSampleSpec(_dev(ph), E, nu, macro, eps))
+    res, status, sec = fe.solve_batched(samples, tol, green=op, scheme=scheme, precision=precision,
+                                        max_iter=max_iter)
+    torch.cuda.synchronize()
+    return res, status, sec, [e.cpu().numpy() for e in outs]
+
+
+@pytest.mark.parametrize("op,scheme,precision,tol", [
+    ("R", "AS", "fp32", 1e-5),
+    ("W", "DS", "fp32", 1e-3),  # float32 DS at contrast 100 stalls near 1.4e-4 (float32 tau)
+    ("R", "DS", "fp64", 1e-8),
+    ("W", "AS", "fp64", 1e-9),
+])
+def test_batched_samples_match_single_solves_bitwise(op, scheme, precision, tol):
+    specs = _samples()
+    res, status, sec, eps = _batched(specs, op, scheme, precision, tol, 3000)
+    assert status == fe.FE_OK, [(r.status, r.iterations, r.eta) for r in res]
+    assert sec > 0
+    its = []
+    for (ph, E, nu, macro), rb, eb in zip(specs, res, eps):
+        rs, es = _single(ph, E, nu, macro, op, scheme, precision, tol, 3000)
+        assert rs.status == fe.FE_OK and rb.status == fe.FE_OK
+        assert rb.iterations == rs.iterations
+        assert rb.eta == rs.eta
+        assert rb.eta <= tol
+        assert np.array_equal(eb, es)
+        assert np.array_equal(rb.mean_stress, rs.mean_stress)
+        assert np.isclose(rb.eta_verify_fp64, rs.eta_verify_fp64, rtol=1e-12, atol=0)
+        its.append(rb.iterations)
+    assert len(set(its)) > 1  # uneven: samples retire at different iterations
+
+
+def test_batched_float64_sample_matches_the_oracle():
+    specs = _samples()
+    res, status, _, eps = _batched(specs, "R", "AS", "fp64", 1e-8, 3000)
+    assert status == fe.FE_OK
+    ph, E, nu, macro = specs[1]
+    k = res[1].iterations
+    ref = O.solve(ph, E, nu, macro, op="R", scheme="AS", tol=1e-300, max_iter=k)
+    assert ref.iterations == k
+    rel = np.linalg.norm(eps[1] - O.tensor_to_voigt(ref.eps)) / np.linalg.norm(O.tensor_to_voigt(ref.eps))
+    assert rel < 1e-12
+    assert np.isclose(res[1].eta, ref.eta_history[k], rtol=1e-10, atol=1e-14)
+
+
+def test_iteration_cap_retires_only_the_capped_samples():
+    """The high-contrast sample needs many more direct-scheme iterations; with
+    a cap between the counts it alone ends FE_NOT_CONVERGED at the cap."""
+    specs = _samples()
+    free, _, _, _ = _batched(specs, "R", "DS", "fp64", 1e-6, 5000)
+    its = sorted(r.iterations for r in free)
+    cap = (its[-2] + its[-1]) // 2
+    assert its[-2] < cap < its[-1]
+    res, status, _, eps = _batched(specs, "R", "DS", "fp64", 1e-6, cap)
+    assert status == fe.FE_NOT_CONVERGED
+    for rf, rc, (ph, E, nu, macro), ec in zip(free, res, specs, eps):
+        if rf.iterations <= cap:
+            assert rc.status == fe.FE_OK and rc.iterations == rf.iterations
+        else:
+            assert rc.status == fe.FE_NOT_CONVERGED and rc.iterations == cap
+            rs, es = _single(ph, E, nu, macro, "R", "DS", "fp64", 1e-6, cap)
+            assert rs.status == fe.FE_NOT_CONVERGED and rs.iterations == cap
+            assert np.array_equal(ec, es)
+
+
+def test_batched_rejects_bad_labels():
+    specs = _samples()
+    ph, E, nu, macro = specs[0]
+    bad = ph.copy()
+    bad[3, 4, 5] = 2  # two phases declared
+    samples = [fe.BatchSampleSpec(_dev(bad), E, nu, macro)]
+    _, status, _ = fe.solve_batched(samples, 1e-6, raise_on_error=False)
+    assert status == fe.FE_ERR_INVALID_ARG
+    assert "label" in fe.last_error()
