@@ -59,6 +59,30 @@ def pass_bytes(L: int, elem: int = 4):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ASR_fp32_512.json")
+
+
+def measured_traffic(pass_name: str, L: int):
+    """HBM bytes per launch of a pass from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE counters (scaled by a 1 GiB copy's readings), or None when the
+    counters were taken on another grid or the kernel's sources changed since."""
+    import hashlib
+
+    if L != 512 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh).get("kernels", {}).get(pass_name)
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_1412_8398_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return int(round(rec["bytes"]))
+
+
 def cpu_baseline(L_sample: int, iters: int):
     """The FP64 oracle on the host cores: AS with the rotated operator on an
     L_sample^3 sample of the same recipe, `iters` iterations."""
@@ -155,7 +179,7 @@ def main():
         "peak": PEAK_HBM_GBS,
         "unit": "GB/s",
         "frac": round(passes[dom]["gbs"] / PEAK_HBM_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(dom, L),
     }
     step_bytes = sum(pb.values())
     iter_gbs = step_bytes * K / wall / 1e9
