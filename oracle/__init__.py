@@ -19,6 +19,12 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
                               (W, R), DS == AS fixed point
   effective_stiffness         Voigt/Reuss bounds, laminate closed form,
                               the paper's printed limit 1.208 (weak pin)
+  unet (warm-start network, not part of the paper)
+    conv3                     direct loop sum, FFT circular correlation
+    conv3_backward            adjoint identities
+    pool / up                 adjoint identities, values
+    loss_and_grad             central finite differences of every tensor
+    adam_step                 closed-form bias-corrected first step
 No function is left unpinned.
 """
 from .homogenization import *  # noqa: F401,F403
