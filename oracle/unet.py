@@ -39,10 +39,19 @@ components of eps_bar broadcast over the grid (tensor Voigt order 11, 22, 33,
 Parameters in canonical order (each weight followed by its bias):
   LAYERS below, then the head (16, 6) and (6,).
 
+Storage precision: ``forward`` and ``loss_and_grad`` take an optional
+``store`` function applied wherever the network keeps a tensor in memory
+(input features, every convolution and pooling output, every activation
+gradient handed from one layer to the next, up- and pool-gradients).  The
+default keeps float64 throughout; ``bf16`` (round to nearest even to 8
+significant bits) reproduces a network that stores those tensors in bfloat16
+while accumulating at higher precision.
+
 Pins (tests/test_oracle_unet.py): conv3 against a direct 7-loop sum and a
 circular FFT convolution; pool/up adjointness; every gradient of the loss
 against central finite differences on a small network and grid; Adam against
-its closed-form first step and a hand-iterated scalar sequence.
+its closed-form first step and a hand-iterated scalar sequence; bf16 against
+hand-rounded values.
 """
 from __future__ import annotations
 
@@ -51,7 +60,7 @@ import numpy as np
 __all__ = [
     "LAYERS", "TAPS", "param_shapes", "n_params", "init_params", "unflatten", "flatten",
     "conv3", "conv3_backward", "pool", "pool_backward", "up", "up_backward", "features",
-    "forward", "loss_and_grad", "adam_step", "AdamState",
+    "forward", "loss_and_grad", "adam_step", "AdamState", "bf16",
 ]
 
 # (name, c_in, c_out) of the fourteen 3^3 convolutions
@@ -113,6 +122,19 @@ def init_params(rng: np.random.Generator):
 # ---------------------------------------------------------------------------
 # layers
 # ---------------------------------------------------------------------------
+
+def _ident(a):
+    return a
+
+
+def bf16(a):
+    """Round to the nearest bfloat16 (8 significant bits, ties to even), returned
+    as float64: x = m 2^e with |m| in [1, 2) is rounded to a multiple of 2^(e-7)."""
+    a = np.asarray(a, dtype=np.float64)
+    m, e = np.frexp(a)  # a = m 2^e, |m| in [0.5, 1)
+    q = np.round(m * 256.0)  # numpy rounds halves to even
+    return np.ldexp(q / 256.0, e)
+
 
 def _shift(x, off):
     """x[v + off] on the periodic grid (axes 1, 2, 3 = z, y, x)."""
@@ -177,25 +199,27 @@ def features(phase, E, nu, macro):
 # network
 # ---------------------------------------------------------------------------
 
-def _block(x, p, a, bname, cache):
-    ya = np.maximum(conv3(x, p[a + ".w"], p[a + ".b"]), 0.0)
-    yb = np.maximum(conv3(ya, p[bname + ".w"], p[bname + ".b"]), 0.0)
+def _block(x, p, a, bname, cache, store):
+    ya = store(np.maximum(conv3(x, p[a + ".w"], p[a + ".b"]), 0.0))
+    yb = store(np.maximum(conv3(ya, p[bname + ".w"], p[bname + ".b"]), 0.0))
     cache[a] = (x, ya)
     cache[bname] = (ya, yb)
     return yb
 
 
-def forward(params, x, macro):
+def forward(params, x, macro, store=None):
     """Mean-corrected strain prediction (B, nz, ny, nx, 6) and the cache the
     backward pass needs."""
-    c = {}
-    e1 = _block(x, params, "enc1a", "enc1b", c)
-    e2 = _block(pool(e1), params, "enc2a", "enc2b", c)
-    e3 = _block(pool(e2), params, "enc3a", "enc3b", c)
-    bt = _block(pool(e3), params, "bota", "botb", c)
-    d3 = _block(np.concatenate([up(bt), e3], axis=-1), params, "dec3a", "dec3b", c)
-    d2 = _block(np.concatenate([up(d3), e2], axis=-1), params, "dec2a", "dec2b", c)
-    d1 = _block(np.concatenate([up(d2), e1], axis=-1), params, "dec1a", "dec1b", c)
+    s = store or _ident
+    c = {"store": s}
+    x = s(x)
+    e1 = _block(x, params, "enc1a", "enc1b", c, s)
+    e2 = _block(s(pool(e1)), params, "enc2a", "enc2b", c, s)
+    e3 = _block(s(pool(e2)), params, "enc3a", "enc3b", c, s)
+    bt = _block(s(pool(e3)), params, "bota", "botb", c, s)
+    d3 = _block(np.concatenate([up(bt), e3], axis=-1), params, "dec3a", "dec3b", c, s)
+    d2 = _block(np.concatenate([up(d3), e2], axis=-1), params, "dec2a", "dec2b", c, s)
+    d1 = _block(np.concatenate([up(d2), e1], axis=-1), params, "dec1a", "dec1b", c, s)
     p = d1 @ params["head.w"] + params["head.b"]
     macro = np.asarray(macro, dtype=np.float64).reshape(-1, 1, 1, 1, 6)
     pred = p - p.mean(axis=(1, 2, 3), keepdims=True) + macro
@@ -204,21 +228,23 @@ def forward(params, x, macro):
 
 
 def _block_backward(g, params, a, bname, cache, grads):
+    s = cache["store"]
     ya_in, yb = cache[bname]
     g = g * (yb > 0)
     gx, gw, gb = conv3_backward(ya_in, params[bname + ".w"], g)
     grads[bname + ".w"], grads[bname + ".b"] = gw, gb
     x_in, ya = cache[a]
-    g = gx * (ya > 0)
+    g = s(gx) * (ya > 0)
     gx, gw, gb = conv3_backward(x_in, params[a + ".w"], g)
     grads[a + ".w"], grads[a + ".b"] = gw, gb
-    return gx
+    return s(gx)
 
 
-def loss_and_grad(params, x, macro, target):
+def loss_and_grad(params, x, macro, target, store=None):
     """Loss (mean squared error of the mean-corrected prediction) and its
     gradient with respect to every parameter."""
-    pred, c = forward(params, x, macro)
+    pred, c = forward(params, x, macro, store)
+    s = c["store"]
     diff = pred - target
     loss = float(np.mean(diff ** 2))
     g = 2.0 * diff / diff.size
@@ -228,17 +254,17 @@ def loss_and_grad(params, x, macro, target):
     d1 = c["d1"]
     grads["head.w"] = d1.reshape(-1, d1.shape[-1]).T @ g.reshape(-1, 6)
     grads["head.b"] = g.reshape(-1, 6).sum(axis=0)
-    g = g @ params["head.w"].T
+    g = s(g @ params["head.w"].T)
     g = _block_backward(g, params, "dec1a", "dec1b", c, grads)
     g_up, g_e1 = g[..., :32], g[..., 32:]
-    g = _block_backward(up_backward(g_up), params, "dec2a", "dec2b", c, grads)
+    g = _block_backward(s(up_backward(g_up)), params, "dec2a", "dec2b", c, grads)
     g_up, g_e2 = g[..., :64], g[..., 64:]
-    g = _block_backward(up_backward(g_up), params, "dec3a", "dec3b", c, grads)
+    g = _block_backward(s(up_backward(g_up)), params, "dec3a", "dec3b", c, grads)
     g_up, g_e3 = g[..., :128], g[..., 128:]
-    g = _block_backward(up_backward(g_up), params, "bota", "botb", c, grads)
-    g = _block_backward(pool_backward(g) + g_e3, params, "enc3a", "enc3b", c, grads)
-    g = _block_backward(pool_backward(g) + g_e2, params, "enc2a", "enc2b", c, grads)
-    _block_backward(pool_backward(g) + g_e1, params, "enc1a", "enc1b", c, grads)
+    g = _block_backward(s(up_backward(g_up)), params, "bota", "botb", c, grads)
+    g = _block_backward(s(pool_backward(g) + g_e3), params, "enc3a", "enc3b", c, grads)
+    g = _block_backward(s(pool_backward(g) + g_e2), params, "enc2a", "enc2b", c, grads)
+    _block_backward(s(pool_backward(g) + g_e1), params, "enc1a", "enc1b", c, grads)
     return loss, grads
 
 

@@ -18,6 +18,7 @@ __all__ = [
     "FE_OK", "FE_NOT_CONVERGED", "FE_DIVERGED", "FE_ERR_INVALID_ARG", "FE_ERR_UNSUPPORTED",
     "FE_ERR_OOM", "FE_ERR_DEVICE", "GREEN", "SCHEME", "PRECISION", "FeError", "Plan", "Result",
     "load_library", "library_path", "status_string", "last_error", "BatchSampleSpec", "solve_batched",
+    "UNet", "conv3_forward", "conv3_backward_data", "conv3_backward_weight",
 ]
 
 FE_OK, FE_NOT_CONVERGED, FE_DIVERGED = 0, 1, 2
@@ -341,3 +342,188 @@ def solve_batched(samples, tol, green="R", scheme="AS", precision="fp32", max_it
     out = [Result(r.status, r.iterations, r.eta, r.eta_verify_fp64, np.array(r.mean_stress[:]), sec.value)
            for r in res] if s >= 0 else []
     return out, s, sec.value
+
+
+# ---------------------------------------------------------------------------
+# warm-start U-Net (include/fe_nn.h)
+# ---------------------------------------------------------------------------
+class FeUnetConfig(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("seed", C.c_uint64), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("adam_eps", C.c_float), ("hip_stream", C.c_void_p)]
+
+
+class FeUnetBatch(C.Structure):
+    _fields_ = [("grid", FeGrid), ("batch", C.c_int32), ("phase", C.c_void_p), ("materials", C.POINTER(FeMaterials)),
+                ("macro_strain", C.POINTER(C.c_double))]
+
+
+class FeNNConvShape(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("batch", C.c_int32), ("c_in", C.c_int32),
+                ("c_out", C.c_int32)]
+
+
+_NN_BOUND = False
+
+
+def _bind_nn(lib):
+    global _NN_BOUND
+    if _NN_BOUND:
+        return lib
+    P = C.c_void_p
+    lib.fe_unet_config_default.argtypes = [C.POINTER(FeUnetConfig)]
+    lib.fe_unet_config_default.restype = None
+    lib.fe_unet_create.argtypes = [C.POINTER(FeUnetConfig), C.POINTER(P)]
+    lib.fe_unet_create.restype = C.c_int
+    lib.fe_unet_destroy.argtypes = [P]
+    lib.fe_unet_destroy.restype = None
+    lib.fe_unet_param_count.argtypes = []
+    lib.fe_unet_param_count.restype = C.c_int64
+    for f in ("fe_unet_get_params", "fe_unet_get_grads"):
+        getattr(lib, f).argtypes = [P, C.POINTER(C.c_float)]
+        getattr(lib, f).restype = C.c_int
+    lib.fe_unet_set_params.argtypes = [P, C.POINTER(C.c_float)]
+    lib.fe_unet_set_params.restype = C.c_int
+    lib.fe_unet_predict.argtypes = [P, C.POINTER(FeUnetBatch), P, C.POINTER(C.c_double)]
+    lib.fe_unet_predict.restype = C.c_int
+    for f in ("fe_unet_loss_grad", "fe_unet_train_step"):
+        getattr(lib, f).argtypes = [P, C.POINTER(FeUnetBatch), P, C.c_int32, C.POINTER(C.c_double)]
+        getattr(lib, f).restype = C.c_int
+    lib.fe_nn_conv3_forward.argtypes = [C.POINTER(FeNNConvShape), P, P, P, C.c_int32, P, P]
+    lib.fe_nn_conv3_forward.restype = C.c_int
+    lib.fe_nn_conv3_backward_data.argtypes = [C.POINTER(FeNNConvShape), P, P, P, P, P]
+    lib.fe_nn_conv3_backward_data.restype = C.c_int
+    lib.fe_nn_conv3_backward_weight.argtypes = [C.POINTER(FeNNConvShape), P, P, P, P, P, P]
+    lib.fe_nn_conv3_backward_weight.restype = C.c_int
+    _NN_BOUND = True
+    return lib
+
+
+def _check(s, where):
+    if s < 0 or s == FE_DIVERGED:
+        raise FeError(s, where)
+    return s
+
+
+def _shape(x, c_in, c_out):
+    B, nz, ny, nx = (int(v) for v in x.shape[:4])
+    return FeNNConvShape(nx, ny, nz, B, int(c_in), int(c_out))
+
+
+def conv3_forward(x, w, b=None, relu=True, stream=None):
+    """fe_nn_conv3_forward on device tensors: x (B, nz, ny, nx, c_in) bfloat16,
+    w (27, c_in, c_out) float32, b (c_out,) float32 -> y bfloat16."""
+    import torch
+    lib = _bind_nn(load_library())
+    y = torch.empty(tuple(x.shape[:4]) + (int(w.shape[2]),), dtype=torch.bfloat16, device=x.device)
+    _check(lib.fe_nn_conv3_forward(C.byref(_shape(x, w.shape[1], w.shape[2])), _ptr(x), _ptr(w), _ptr(b),
+                                   1 if relu else 0, _ptr(y), stream), "fe_nn_conv3_forward")
+    return y
+
+
+def conv3_backward_data(dy, w, y_mask=None, stream=None):
+    import torch
+    lib = _bind_nn(load_library())
+    dx = torch.empty(tuple(dy.shape[:4]) + (int(w.shape[1]),), dtype=torch.bfloat16, device=dy.device)
+    _check(lib.fe_nn_conv3_backward_data(C.byref(_shape(dy, w.shape[1], w.shape[2])), _ptr(dy), _ptr(y_mask), _ptr(w),
+                                         _ptr(dx), stream), "fe_nn_conv3_backward_data")
+    return dx
+
+
+def conv3_backward_weight(x, dy, y_mask=None, stream=None):
+    import torch
+    lib = _bind_nn(load_library())
+    c_in, c_out = int(x.shape[4]), int(dy.shape[4])
+    dw = torch.empty((27, c_in, c_out), dtype=torch.float32, device=x.device)
+    db = torch.empty((c_out,), dtype=torch.float32, device=x.device)
+    _check(lib.fe_nn_conv3_backward_weight(C.byref(_shape(x, c_in, c_out)), _ptr(x), _ptr(dy), _ptr(y_mask), _ptr(dw),
+                                           _ptr(db), stream), "fe_nn_conv3_backward_weight")
+    return dw, db
+
+
+class UNet:
+    """The warm-start network (fe_unet_*): predict, loss/gradient, Adam steps."""
+
+    def __init__(self, seed=1412839801, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, stream=None):
+        lib = _bind_nn(load_library())
+        cfg = FeUnetConfig()
+        lib.fe_unet_config_default(C.byref(cfg))
+        cfg.seed = int(seed)
+        cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps = float(lr), float(beta1), float(beta2), float(adam_eps)
+        cfg.hip_stream = stream
+        h = C.c_void_p()
+        _check(lib.fe_unet_create(C.byref(cfg), C.byref(h)), "fe_unet_create")
+        self._h, self._lib = h, lib
+        self.n_params = int(lib.fe_unet_param_count())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fe_unet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(self._lib.fe_unet_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float))), "fe_unet_get_params")
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        if p.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {p.size}")
+        _check(self._lib.fe_unet_set_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float))), "fe_unet_set_params")
+
+    def get_grads(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(self._lib.fe_unet_get_grads(self._h, out.ctypes.data_as(C.POINTER(C.c_float))), "fe_unet_get_grads")
+        return out
+
+    @staticmethod
+    def _batch(phase, E, nu, macro):
+        """phase: device uint8 (B, nz, ny, nx); E, nu: per-sample phase tables; macro (B, 6)."""
+        B, nz, ny, nx = (int(v) for v in phase.shape)
+        mats = (FeMaterials * B)()
+        keep = []
+        for s in range(B):
+            m, k = _materials(E[s], nu[s])
+            mats[s] = m
+            keep.append(k)
+        mac = np.ascontiguousarray(np.asarray(macro, dtype=np.float64).reshape(B, 6))
+        keep.append(mac)
+        b = FeUnetBatch(FeGrid(nx, ny, nz), B, _ptr(phase), mats, mac.ctypes.data_as(C.POINTER(C.c_double)))
+        keep.append(mats)
+        return b, keep
+
+    def predict(self, phase, E, nu, macro, out=None):
+        """Predicted strain, device float32 (B, 6, nz, ny, nx); returns (out, seconds)."""
+        import torch
+        b, keep = self._batch(phase, E, nu, macro)
+        if out is None:
+            out = torch.empty((b.batch, 6) + tuple(phase.shape[1:]), dtype=torch.float32, device=phase.device)
+        sec = C.c_double(0.0)
+        _check(self._lib.fe_unet_predict(self._h, C.byref(b), _ptr(out), C.byref(sec)), "fe_unet_predict")
+        del keep
+        return out, sec.value
+
+    def loss_grad(self, phase, E, nu, macro, target):
+        import torch
+        b, keep = self._batch(phase, E, nu, macro)
+        loss = C.c_double(0.0)
+        _check(self._lib.fe_unet_loss_grad(self._h, C.byref(b), _ptr(target), 1 if target.dtype == torch.bfloat16 else 0,
+                                           C.byref(loss)), "fe_unet_loss_grad")
+        del keep
+        return loss.value
+
+    def train_step(self, phase, E, nu, macro, target):
+        import torch
+        b, keep = self._batch(phase, E, nu, macro)
+        loss = C.c_double(0.0)
+        _check(self._lib.fe_unet_train_step(self._h, C.byref(b), _ptr(target),
+                                            1 if target.dtype == torch.bfloat16 else 0, C.byref(loss)),
+               "fe_unet_train_step")
+        del keep
+        return loss.value

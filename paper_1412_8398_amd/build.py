@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfe.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["fe_pass_x6.hip", "fe_pass_x3.hip", "fe_pass_z.hip", "fe_pass_y.hip", "fe_pointwise.hip", "fe_api.hip"]
+SOURCES = ["fe_pass_x6.hip", "fe_pass_x3.hip", "fe_pass_z.hip", "fe_pass_y.hip", "fe_pointwise.hip", "fe_api.hip",
+           "fe_nn_conv.hip", "fe_nn_ops.hip", "fe_unet.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -42,7 +43,7 @@ def hipcc() -> str:
 
 def _newest_header() -> float:
     hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
-    hdrs.append(os.path.join(INCLUDE, "fe.h"))
+    hdrs += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
     return max(os.path.getmtime(h) for h in hdrs)
 
 

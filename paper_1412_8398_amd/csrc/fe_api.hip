@@ -11,32 +11,10 @@
 
 #include "../../include/fe.h"
 #include "fe_fft.h"
+#include "fe_error.h"
 #include "fe_kernels.h"
 
 using namespace fe;
-
-// ---------------------------------------------------------------------------
-// errors
-// ---------------------------------------------------------------------------
-static thread_local std::string g_last_error;
-
-static fe_status fail(fe_status s, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_last_error = buf;
-  return s;
-}
-
-#define HIP_TRY(expr)                                                                       \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return fail(e_ == hipErrorOutOfMemory ? FE_ERR_OOM : FE_ERR_DEVICE, "%s: %s (%s:%d)", \
-                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                         \
-  } while (0)
 
 // ---------------------------------------------------------------------------
 // host-side tables (float64)
@@ -265,9 +243,9 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
   p->div_blocks = (int)(db > kMaxReduceBlocks ? kMaxReduceBlocks : db);
 
   auto cleanup_fail = [&](fe_status s) {
-    std::string keep = g_last_error;
+    std::string keep = last_error_text();
     fe_plan_destroy(p);
-    g_last_error = keep;
+    last_error_text() = keep;
     return s;
   };
   if (hipGetDevice(&p->device) != hipSuccess) return cleanup_fail(fail(FE_ERR_DEVICE, "no HIP device"));
@@ -785,7 +763,7 @@ extern "C" const char* fe_status_string(fe_status s) {
   return "FE_UNKNOWN_STATUS";
 }
 
-extern "C" const char* fe_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* fe_last_error(void) { return last_error_text().c_str(); }
 
 // ---------------------------------------------------------------------------
 // batched solves

@@ -154,3 +154,31 @@ def test_adam_first_step_and_a_scalar_sequence():
 def test_parameter_count():
     n = sum(27 * ci * co + co for _, ci, co in U.LAYERS) + 16 * 6 + 6
     assert U.n_params() == n == 1_462_694
+
+
+def test_bf16_rounding_by_hand():
+    one = 1.0
+    assert U.bf16(one + 2.0 ** -8) == 1.0                      # tie -> even
+    assert U.bf16(one + 3 * 2.0 ** -8) == one + 2.0 ** -6      # tie -> even (upward)
+    assert U.bf16(one + 2.0 ** -8 + 2.0 ** -20) == one + 2.0 ** -7
+    assert U.bf16(-(one + 2.0 ** -8 + 2.0 ** -20)) == -(one + 2.0 ** -7)
+    assert U.bf16(2.0 - 2.0 ** -8) == 2.0                      # tie -> even, carries into the next binade
+    assert U.bf16(0.0) == 0.0
+    r = _rng(8).standard_normal(1000) * 10.0 ** _rng(9).uniform(-30, 30, 1000)
+    q = U.bf16(r)
+    assert np.all(np.abs(q - r) <= 2.0 ** -8 * np.abs(r))  # unit roundoff of 8 significant bits
+    # 8 significant bits: q / 2^(floor(log2 |q|) - 7) is an integer
+    e = np.floor(np.log2(np.abs(q)))
+    assert np.all(np.ldexp(q, (7 - e).astype(int)) == np.round(np.ldexp(q, (7 - e).astype(int))))
+
+
+def test_storage_rounding_hook_defaults_to_float64():
+    r = _rng(10)
+    p = U.init_params(r)
+    x = r.standard_normal((1, 8, 8, 8, 8))
+    macro = r.standard_normal((1, 6))
+    a, _ = U.forward(p, x, macro)
+    b, _ = U.forward(p, x, macro, store=lambda t: t)
+    c, _ = U.forward(p, x, macro, store=U.bf16)
+    assert np.array_equal(a, b)
+    assert 0 < np.linalg.norm(c - a) <= 3e-2 * np.linalg.norm(a - macro.reshape(1, 1, 1, 1, 6))
