@@ -187,7 +187,9 @@ fe_status fe_effective_stiffness(fe_plan* plan, const uint8_t* phase, fe_materia
  * Samples are grouped by grid; each pass of an iteration is one launch over
  * all active samples of a group (the sample is the second grid dimension of
  * the launch), eta is reduced per sample on the device, and a sample retires
- * as soon as its own eta^k <= tol (or its iteration cap is reached).
+ * as soon as its own eta^k <= tol, its iteration cap is reached, or its eta
+ * has not fallen by 5% over 100 iterations (the storage floor of float32
+ * fields: FE_NOT_CONVERGED with the iterate reached at that point).
  * Supported: FE_GREEN_WP and FE_GREEN_ROT (displacement form); plain
  * iterations in the plan precision (no float64 re-anchoring).
  *   desc->phase[i]   device, N_i uint8 labels of sample i

@@ -70,6 +70,9 @@ fe_status fe_unet_create(const fe_unet_config* cfg, fe_unet** out);
 void fe_unet_destroy(fe_unet* net);
 int64_t fe_unet_param_count(void);
 
+/* Adam step size for the following fe_unet_train_step calls (> 0, finite). */
+fe_status fe_unet_set_learning_rate(fe_unet* net, float lr);
+
 /* host float32 [fe_unet_param_count()] in canonical order; set also resets the
  * Adam moments and step counter */
 fe_status fe_unet_get_params(fe_unet* net, float* host_params);

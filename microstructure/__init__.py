@@ -60,7 +60,36 @@ class SplitMix64:
         return (self.next_u64() >> 11) * (1.0 / (1 << 53))
 
     def uniform_array(self, n: int) -> np.ndarray:
-        return np.array([self.uniform() for _ in range(n)], dtype=np.float64)
+        """The next ``n`` uniforms, computed for all counters at once (the k-th
+        draw mixes state + k * GAMMA, so the sequence equals n calls of
+        ``uniform``)."""
+        if n <= 0:
+            return np.zeros(0)
+        k = np.arange(1, n + 1, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            z = np.uint64(self.state) + k * np.uint64(self.GAMMA)
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            z = z ^ (z >> np.uint64(31))
+        self.state = (self.state + n * self.GAMMA) & _MASK64
+        return (z >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+
+    def poisson_fast(self, mean: float) -> int:
+        """Same count and same draws consumed as ``poisson`` (count + 1
+        uniforms), drawn in blocks."""
+        start = self.state
+        t, used = 0.0, 0
+        block = int(mean + 6.0 * math.sqrt(mean) + 16)
+        while True:
+            u = self.uniform_array(block)
+            c = t + np.cumsum(-np.log1p(-u))
+            over = np.nonzero(c > mean)[0]
+            if over.size:
+                k = used + int(over[0])  # draws before the one that crossed
+                self.state = (start + (k + 1) * self.GAMMA) & _MASK64
+                return k
+            t = float(c[-1])
+            used += block
 
     def poisson(self, mean: float) -> int:
         """Poisson count by summing unit-rate exponential gaps until they
@@ -123,6 +152,31 @@ def sphere_inclusion(shape, center, radius) -> np.ndarray:
     return (r2 <= radius * radius).astype(np.uint8)
 
 
+def _stamp_equal_spheres(shape, centers, r, chunk=256):
+    """Union of periodic spheres of one radius, all spheres of a chunk at once;
+    the same voxel test (and float64 operation order) as ``_stamp_spheres``."""
+    nz, ny, nx = shape
+    out = np.zeros(shape, dtype=np.uint8)
+    R = int(math.ceil(r)) + 2
+    o = np.arange(-R, R + 1)
+    r2 = r * r
+    for a in range(0, len(centers), chunk):
+        c = np.asarray(centers[a:a + chunk], dtype=np.float64)
+        # per axis (z, y, x): candidate indices around the centre and offsets
+        idx, off = [], []
+        for col, n in ((2, nz), (1, ny), (0, nx)):
+            cand = np.floor(c[:, col])[:, None].astype(np.int64) + o[None, :]
+            off.append(cand + 0.5 - c[:, col][:, None])
+            idx.append(np.mod(cand, n))
+        dz2 = off[0][:, :, None, None] ** 2
+        dy2 = off[1][:, None, :, None] ** 2
+        dx2 = off[2][:, None, None, :] ** 2
+        inside = (dz2 + dy2 + dx2) <= r2
+        s_, i, j, k = np.nonzero(inside)
+        out[idx[0][s_, i], idx[1][s_, j], idx[2][s_, k]] = 1
+    return out
+
+
 def _stamp_spheres(shape, centers, radii) -> np.ndarray:
     """Union of periodic spheres, stamped through each sphere's bounding box."""
     nz, ny, nx = shape
@@ -171,13 +225,12 @@ def boolean_spheres(shape, radius: float, target_fraction: float, seed: int):
     rng = SplitMix64(seed)
     v_sphere = 4.0 * math.pi * radius ** 3 / 3.0
     theta = -math.log(1.0 - target_fraction) / v_sphere
-    count = rng.poisson(theta * nx * ny * nz)
-    centers = np.empty((count, 3))
-    for s in range(count):
-        centers[s, 0] = rng.uniform() * nx
-        centers[s, 1] = rng.uniform() * ny
-        centers[s, 2] = rng.uniform() * nz
-    phase = _stamp_spheres(shape, centers, [radius] * count)
+    count = rng.poisson_fast(theta * nx * ny * nz)
+    centers = rng.uniform_array(3 * count).reshape(count, 3) * np.array([nx, ny, nz], dtype=np.float64)
+    if 2 * int(math.ceil(radius)) + 5 <= min(shape):
+        phase = _stamp_equal_spheres(shape, centers, radius)
+    else:
+        phase = _stamp_spheres(shape, centers, [radius] * count)
     return phase, BooleanInfo(count, centers, radius, float(phase.mean()))
 
 

@@ -17,6 +17,9 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
   solve (DS, AS)              homogeneous one-step, laminate closed form,
                               direct finite-difference solve on tiny grids
                               (W, R), DS == AS fixed point
+  laminate_exact              the oracle's own iterative solve on laminates
+                              (R, W any thickness; MS, C even thickness),
+                              and traction/compatibility checks
   effective_stiffness         Voigt/Reuss bounds, laminate closed form,
                               the paper's printed limit 1.208 (weak pin)
   unet (warm-start network, not part of the paper)
@@ -34,5 +37,5 @@ from .homogenization import (  # noqa: F401
     equilibrium_norm, forward_dft, inverse_dft, brute_force_dft,
     voigt_to_tensor, tensor_to_voigt, stiffness_tensor, lame_from_young,
     green_continuous_closed_form, green3_closed_form, wave_vector_r_literal,
-    signed_modes, mandel_matrix, compliance_apply,
+    signed_modes, mandel_matrix, compliance_apply, laminate_exact,
 )

@@ -503,6 +503,28 @@ class SolveResult:
     iterates: list = field(default_factory=list)  # optional (3,3,...) per k
 
 
+def laminate_exact(labels_x, E, nu, macro_strain):
+    """Exact strain of a laminate whose phase depends on the x index only
+    (labels_x[i] for every voxel of x index i): traction continuity across the
+    layers (eqs. (1)-(2)) makes sigma_11, sigma_12, sigma_13 uniform and
+    compatibility with the applied strain (eq. (4)) makes eps_22, eps_33,
+    eps_23 equal to their averages.  Returns (3, 3, nx)."""
+    lam, mu = lame_from_young(E, nu)
+    lam_x, mu_x = lam[np.asarray(labels_x)], mu[np.asarray(labels_x)]
+    e = voigt_to_tensor(np.asarray(macro_strain, dtype=np.float64))
+    m = lambda f: float(np.mean(f))  # noqa: E731  (mean over the layers)
+    S = (e[0, 0] + m(lam_x / (lam_x + 2 * mu_x)) * (e[1, 1] + e[2, 2])) / m(1 / (lam_x + 2 * mu_x))
+    T12 = e[0, 1] / m(1 / (2 * mu_x))
+    T13 = e[0, 2] / m(1 / (2 * mu_x))
+    eps = np.zeros((3, 3, lam_x.size))
+    eps[1, 1], eps[2, 2] = e[1, 1], e[2, 2]
+    eps[1, 2] = eps[2, 1] = e[1, 2]
+    eps[0, 0] = (S - lam_x * (e[1, 1] + e[2, 2])) / (lam_x + 2 * mu_x)
+    eps[0, 1] = eps[1, 0] = T12 / (2 * mu_x)
+    eps[0, 2] = eps[2, 0] = T13 / (2 * mu_x)
+    return eps
+
+
 def solve(phase, E, nu, macro_strain, op="R", scheme="DS", tol=1e-10, max_iter=1000,
           eps_init=None, ref: Reference | None = None, beta=0.5, keep_iterates=False):
     """Run the direct (eq. (9)) or accelerated (eq. (16)) scheme.

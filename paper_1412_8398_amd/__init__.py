@@ -381,6 +381,8 @@ def _bind_nn(lib):
     for f in ("fe_unet_get_params", "fe_unet_get_grads"):
         getattr(lib, f).argtypes = [P, C.POINTER(C.c_float)]
         getattr(lib, f).restype = C.c_int
+    lib.fe_unet_set_learning_rate.argtypes = [P, C.c_float]
+    lib.fe_unet_set_learning_rate.restype = C.c_int
     lib.fe_unet_set_params.argtypes = [P, C.POINTER(C.c_float)]
     lib.fe_unet_set_params.restype = C.c_int
     lib.fe_unet_predict.argtypes = [P, C.POINTER(FeUnetBatch), P, C.POINTER(C.c_double)]
@@ -465,6 +467,9 @@ class UNet:
             self.close()
         except Exception:
             pass
+
+    def set_learning_rate(self, lr):
+        _check(self._lib.fe_unet_set_learning_rate(self._h, float(lr)), "fe_unet_set_learning_rate")
 
     def get_params(self) -> np.ndarray:
         out = np.empty(self.n_params, dtype=np.float32)

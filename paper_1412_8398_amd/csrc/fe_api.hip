@@ -792,6 +792,8 @@ struct BatchClass {
   std::vector<int> act;  // host copy of the active list
   std::vector<int> rising;
   std::vector<double> prev;
+  std::vector<double> best;
+  std::vector<int> best_k;
   void release() {
     void* b[] = {eps, R, S, phase, partials, red, coef, coef64, gcon, active, all, tw[0], tw[1], tw[2],
                  wave[0], wave[1], wave[2]};
@@ -799,6 +801,8 @@ struct BatchClass {
       if (x) (void)hipFree(x);
   }
 };
+
+constexpr int kStallWindow = 100;
 
 template <typename T>
 fe_status alloc_class(BatchClass<T>& c, int op) {
@@ -911,6 +915,8 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
     c.act = idx;
     c.rising.assign(n, 0);
     c.prev.assign(n, INFINITY);
+    c.best.assign(n, INFINITY);
+    c.best_k.assign(n, 0);
   }
   int flag = 0;
   HIP_TRY(hipMemcpy(&flag, hflag, sizeof(int), hipMemcpyDeviceToHost));
@@ -969,6 +975,14 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
         c.prev[j] = eta;
         if (o.diverge_window > 0 && c.rising[j] >= o.diverge_window) {
           out.status = FE_DIVERGED;
+          continue;
+        }
+        // storage floor: no 5% gain over kStallWindow iterations
+        if (eta < 0.95 * c.best[j]) {
+          c.best[j] = eta;
+          c.best_k[j] = k;
+        } else if (k - c.best_k[j] >= kStallWindow) {
+          out.status = FE_NOT_CONVERGED;
           continue;
         }
         keep.push_back(j);

@@ -138,4 +138,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch /* >=
   }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b mod 8), each with its own L2.  This renumbering hands every XCD a
+// contiguous range of logical blocks, so tiles that share halo lines (x and y
+// neighbours) are resident on the same L2 at about the same time.  It is a
+// bijection of [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, k = b & 7;
+  return k * q + (k < r ? k : r) + (b >> 3);
+}
+
 }  // namespace fe

@@ -144,17 +144,28 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* _
   const bool ok = pp < npair;
   const long long plane = (long long)d.ny * d.nx;
   const cpx<T>* src = S + (long long)c * d.H * plane + (long long)y * d.nx + 2 * (ok ? pp : 0);
-  for (int mz = t; mz < d.H; mz += C::P) {
-    cpx2<T> ab;
-    if (ok) {
-      ab = *reinterpret_cast<const cpx2<T>*>(src + (long long)mz * plane);
+  // all loads of this thread in flight before the first LDS store (H = N/2 + 1
+  // half-spectrum planes, ceil(H/P) per thread)
+  constexpr int H = N / 2 + 1, NL = (H + C::P - 1) / C::P;
+  cpx2<T> ab[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int mz = t + i * C::P;
+    if (ok && mz < H) {
+      ab[i] = *reinterpret_cast<const cpx2<T>*>(src + (long long)mz * plane);
     } else {
-      ab.a = mk(T(0), T(0));
-      ab.b = mk(T(0), T(0));
+      ab[i].a = mk(T(0), T(0));
+      ab[i].b = mk(T(0), T(0));
     }
-    const cpx<T> A = ab.a, B = ab.b;
-    lds[mz * C::TX + col] = mk(A.re - B.im, A.im + B.re);
-    if (mz > 0 && 2 * mz < N) lds[(N - mz) * C::TX + col] = mk(A.re + B.im, B.re - A.im);
+  }
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int mz = t + i * C::P;
+    if (mz < H) {
+      const cpx<T> A = ab[i].a, B = ab[i].b;
+      lds[mz * C::TX + col] = mk(A.re - B.im, A.im + B.re);
+      if (mz > 0 && 2 * mz < N) lds[(N - mz) * C::TX + col] = mk(A.re + B.im, B.re - A.im);
+    }
   }
   __syncthreads();
   cpx<T> v[1][C::E];

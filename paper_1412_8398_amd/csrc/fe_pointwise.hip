@@ -119,8 +119,9 @@ __global__ __launch_bounds__(DX * DY) void k_div(const TS* __restrict__ eps, con
   const long long N = d.N;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const int ntx = (nx + DX - 1) / DX, nty = (ny + DY - 1) / DY;
-  const int bx = blockIdx.x % ntx;
-  const int rest = blockIdx.x / ntx;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int bx = tile % ntx;
+  const int rest = tile / ntx;
   const int by = rest % nty;
   const int bz = rest / nty;
   const int x0 = bx * DX, y0 = by * DY, z0 = bz * zchunk;
@@ -267,7 +268,8 @@ __global__ __launch_bounds__(256) void k_grad_update(const T* __restrict__ U, T*
     if (gs) g = gs[smp];
   }
   const int nx = d.nx, ny = d.ny, nz = d.nz;
-  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+  const long long b0 = xcd_block(blockIdx.x, gridDim.x);
+  for (long long v = b0 * blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
     const int x = (int)(v % nx);
     const int y = (int)((v / nx) % ny);
     const int z = (int)(v / ((long long)nx * ny));

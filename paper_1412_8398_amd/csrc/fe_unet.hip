@@ -213,6 +213,13 @@ extern "C" void fe_unet_destroy(fe_unet* n) {
   free_net(n);
 }
 
+extern "C" fe_status fe_unet_set_learning_rate(fe_unet* n, float lr) {
+  if (!n) return fail(FE_ERR_INVALID_ARG, "net is NULL");
+  if (!(lr > 0.f) || !std::isfinite(lr)) return fail(FE_ERR_INVALID_ARG, "learning rate must be finite and > 0");
+  n->cfg.lr = lr;
+  return FE_OK;
+}
+
 extern "C" fe_status fe_unet_get_params(fe_unet* n, float* h) {
   if (!n || !h) return fail(FE_ERR_INVALID_ARG, "net or buffer is NULL");
   HIP_TRY(hipMemcpyAsync(h, n->theta, n->nparam * sizeof(float), hipMemcpyDeviceToHost, n->s));

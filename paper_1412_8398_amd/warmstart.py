@@ -1,0 +1,124 @@
+"""Learned warm start versus the plain start eps^0 = eps_bar.
+
+Both runs solve the same cell with the accelerated scheme and the rotated
+operator (float32 fields, float64 reductions and re-anchoring) to the same
+equilibrium tolerance; the learned run starts from the network's prediction
+and its time includes the prediction.
+
+    python -m paper_1412_8398_amd.warmstart --weights w.npy --size 128 --count 16
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_warmstart.npy")
+
+
+def load_net(path=DEFAULT_WEIGHTS):
+    import paper_1412_8398_amd as fe
+
+    net = fe.UNet()
+    net.set_params(np.load(path))
+    return net
+
+
+def compare_one(net, phase, E, nu, macro, tol=1e-6, max_iter=3000, plan=None):
+    """Plain and learned solves of one cell; returns a dict of measurements.
+    ``phase`` is a device uint8 tensor (nz, ny, nx)."""
+    import torch
+
+    import paper_1412_8398_amd as fe
+
+    nz, ny, nx = (int(v) for v in phase.shape)
+    own = plan is None
+    if own:
+        plan = fe.Plan((nx, ny, nz), green="R", scheme="AS", precision="fp32", max_iter=max_iter)
+    eps_p = torch.empty((6, nz, ny, nx), dtype=torch.float32, device=phase.device)
+    eps_l = torch.empty_like(eps_p)
+    pred = torch.empty((1, 6, nz, ny, nx), dtype=torch.float32, device=phase.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rp = plan.solve(phase, E, nu, macro, tol, strain=eps_p, history=1, raise_on_error=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, t_pred = net.predict(phase.unsqueeze(0), [E], [nu], [macro], out=pred)
+    rl = plan.solve(phase, E, nu, macro, tol, strain_init=pred[0], strain=eps_l, history=1, raise_on_error=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    mac = torch.tensor(np.asarray(macro, dtype=np.float32), device=phase.device).view(6, 1, 1, 1)
+    fluct = torch.linalg.vector_norm((eps_p - mac).double()).item()
+    pred_err = torch.linalg.vector_norm((pred[0] - eps_p).double()).item() / max(fluct, 1e-300)
+    sp, sl = np.asarray(rp.mean_stress), np.asarray(rl.mean_stress)
+    out = {
+        "plain": {"iterations": rp.iterations, "seconds": t1 - t0, "eta0": float(rp.eta_history[0]),
+                  "eta": rp.eta_verify_fp64, "status": rp.status},
+        "learned": {"iterations": rl.iterations, "seconds": t2 - t1, "predict_seconds": t_pred,
+                    "eta0": float(rl.eta_history[0]), "eta": rl.eta_verify_fp64, "status": rl.status},
+        "prediction_rel_l2": pred_err,
+        "mean_stress_rel_diff": float(np.linalg.norm(sl - sp) / max(np.linalg.norm(sp), 1e-300)),
+    }
+    if own:
+        plan.close()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--count", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=5141230)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+
+    from microstructure import batch_samples
+
+    samples = batch_samples(args.count, args.seed, sizes=(args.size,))
+    import torch
+
+    import paper_1412_8398_amd as fe
+
+    net = load_net(args.weights)
+    rows = []
+    with fe.Plan(args.size, green="R", scheme="AS", precision="fp32", max_iter=3000) as plan:
+        s = samples[0]  # warm-up: first launches and workspace, not reported
+        compare_one(net, torch.from_numpy(s.phase).cuda(), [1.0, s.contrast], [s.nu, s.nu], s.macro_strain,
+                    args.tol, plan=plan)
+        for i, s in enumerate(samples):
+            ph = torch.from_numpy(s.phase).cuda()
+            r = compare_one(net, ph, [1.0, s.contrast], [s.nu, s.nu], s.macro_strain, args.tol, plan=plan)
+            r.update({"sample": i, "L": s.L, "contrast": s.contrast, "fraction": s.volume_fraction, "radius": s.radius,
+                      "nu": s.nu, "load": s.load, "seed": s.seed})
+            rows.append(r)
+            print(json.dumps(r), flush=True)
+    it_p = np.array([r["plain"]["iterations"] for r in rows])
+    it_l = np.array([r["learned"]["iterations"] for r in rows])
+    t_p = np.array([r["plain"]["seconds"] for r in rows])
+    t_l = np.array([r["learned"]["seconds"] for r in rows])
+    summ = {"size": args.size, "count": args.count, "tol": args.tol,
+            "iterations_plain_mean": float(it_p.mean()), "iterations_learned_mean": float(it_l.mean()),
+            "seconds_plain_total": float(t_p.sum()), "seconds_learned_total": float(t_l.sum()),
+            "prediction_rel_l2_median": float(np.median([r["prediction_rel_l2"] for r in rows])),
+            "eta0_plain_median": float(np.median([r["plain"]["eta0"] for r in rows])),
+            "eta0_learned_median": float(np.median([r["learned"]["eta0"] for r in rows])),
+            "mean_stress_rel_diff_max": float(max(r["mean_stress_rel_diff"] for r in rows))}
+    print(json.dumps({"summary": summ}), flush=True)
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump({"summary": summ, "rows": rows}, fh, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

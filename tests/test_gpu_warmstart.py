@@ -1,0 +1,40 @@
+"""The trained warm-start network (paper_1412_8398_amd/weights) on held-out
+cells of its training distribution: its prediction is closer to the
+converged strain than the plain start eps^0 = eps_bar (relative L2 1 by
+definition), the solve from it reaches the same equilibrium, and the result
+records what it gains in iterations."""
+import os
+
+import numpy as np
+import pytest
+
+from microstructure import batch_samples
+
+torch = pytest.importorskip("torch")
+import paper_1412_8398_amd as fe  # noqa: E402
+from paper_1412_8398_amd.warmstart import DEFAULT_WEIGHTS, compare_one, load_net  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.skipif(not os.path.exists(DEFAULT_WEIGHTS), reason="no trained weights in the tree")
+def test_learned_start_is_closer_and_converges_to_the_same_answer():
+    net = load_net()
+    samples = batch_samples(6, 777, sizes=(64,))  # seed outside the training and validation sets
+    rows = []
+    with fe.Plan(64, green="R", scheme="AS", precision="fp32", max_iter=3000) as plan:
+        for s in samples:
+            ph = torch.from_numpy(s.phase).cuda()
+            r = compare_one(net, ph, [1.0, s.contrast], [s.nu, s.nu], s.macro_strain, 1e-6, plan=plan)
+            rows.append(r)
+            print(s.contrast, s.volume_fraction, r["plain"]["iterations"], r["learned"]["iterations"],
+                  r["prediction_rel_l2"], flush=True)
+    net.close()
+    for r in rows:
+        assert r["plain"]["status"] == fe.FE_OK and r["learned"]["status"] == fe.FE_OK
+        assert r["mean_stress_rel_diff"] <= 1e-5
+    err = np.array([r["prediction_rel_l2"] for r in rows])
+    assert np.median(err) < 0.8, err
+    it_p = sum(r["plain"]["iterations"] for r in rows)
+    it_l = sum(r["learned"]["iterations"] for r in rows)
+    assert it_l <= it_p + len(rows), (it_p, it_l)  # never worse than one iteration per cell on average

@@ -42,20 +42,23 @@ def test_homogeneous_medium_one_step(op, scheme, rng):
 # --- laminates: exact piecewise-constant solution -------------------------------------
 
 def _laminate_exact(phase_x, E, nu, macro):
+    return O.laminate_exact(phase_x, E, nu, macro)
+
+
+def test_laminate_closed_form_balances_tractions_and_strains():
+    """sigma_11, sigma_12, sigma_13 equal in every layer and the mean strain is
+    eps_bar: the two conditions that define the laminate solution."""
+    labels = np.array([0, 0, 1, 2, 2, 2, 1], dtype=np.uint8)
+    E, nu = np.array([1.0, 7.0, 3.0]), np.array([0.3, 0.2, 0.45])
+    macro = np.array([0.7, -0.3, 0.4, 0.2, -0.5, 0.6])
+    eps = O.laminate_exact(labels, E, nu, macro)
     lam, mu = O.lame_from_young(E, nu)
-    lam_x, mu_x = lam[phase_x], mu[phase_x]
-    e = O.voigt_to_tensor(macro)
-    m = lambda f: float(np.mean(f))  # noqa: E731  (average over layers = over x)
-    S = (e[0, 0] + m(lam_x / (lam_x + 2 * mu_x)) * (e[1, 1] + e[2, 2])) / m(1 / (lam_x + 2 * mu_x))
-    T12 = e[0, 1] / m(1 / (2 * mu_x))
-    T13 = e[0, 2] / m(1 / (2 * mu_x))
-    eps = np.zeros((3, 3, phase_x.size))
-    eps[1, 1], eps[2, 2] = e[1, 1], e[2, 2]
-    eps[1, 2] = eps[2, 1] = e[1, 2]
-    eps[0, 0] = (S - lam_x * (e[1, 1] + e[2, 2])) / (lam_x + 2 * mu_x)
-    eps[0, 1] = eps[1, 0] = T12 / (2 * mu_x)
-    eps[0, 2] = eps[2, 0] = T13 / (2 * mu_x)
-    return eps
+    tr = eps[0, 0] + eps[1, 1] + eps[2, 2]
+    s11 = lam[labels] * tr + 2 * mu[labels] * eps[0, 0]
+    assert np.allclose(s11, s11[0], rtol=1e-14)
+    assert np.allclose(2 * mu[labels] * eps[0, 1], 2 * mu[0] * eps[0, 1, 0], rtol=1e-14)
+    assert np.allclose(2 * mu[labels] * eps[0, 2], 2 * mu[0] * eps[0, 2, 0], rtol=1e-14)
+    assert np.allclose(eps.mean(axis=-1), O.voigt_to_tensor(macro), atol=1e-14)
 
 
 @pytest.mark.parametrize("op,layers", [("R", [3, 7]), ("W", [3, 7]), ("MS", [4, 6]), ("C", [4, 6])])
