@@ -43,7 +43,9 @@ def make_phase(L: int):
 
 def pass_bytes(L: int, elem: int = 4):
     """Algorithmic HBM bytes of one launch of each pass (displacement form,
-    3-component spectra, accelerated scheme), for an L^3 grid."""
+    3-component spectra, accelerated scheme), for an L^3 grid.  "pointwise"
+    (the stand-alone divergence) runs once per solve and after each float64
+    re-anchor; every other iteration gets it from the fused "update"."""
     N = L ** 3
     H = L // 2 + 1
     spec = 3 * H * L * L * 2 * elem        # 3 half spectra along z, complex
@@ -56,7 +58,8 @@ def pass_bytes(L: int, elem: int = 4):
         "xgreen": 2 * spec,
         "yinv": 2 * spec,
         "zinv": spec + real3,                         # read half spectra; write U
-        "update": real3 + strain + N + strain,        # read U, eps, phase; write eps
+        # fused strain update and divergence: read U, eps^k, phase; write eps^(k+1), D
+        "update": real3 + strain + N + strain + real3,
     }
 
 

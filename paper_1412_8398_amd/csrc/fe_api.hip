@@ -5,7 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -117,6 +119,10 @@ struct fe_plan {
   void* dsig_hi = nullptr;   // divergence of the anchor stress, 3 planes
   double* d64 = nullptr;     // float64 divergence / displacement, 3 planes
   cpx<double>* s64 = nullptr;  // float64 half spectra, 3 components
+  void* dlt_alt = nullptr;     // second correction buffer (fused update + divergence)
+  // displacement form: second iterate and divergence buffers (allocated on first use)
+  void* eps_alt = nullptr;
+  void* R2 = nullptr;
 };
 
 // Optional per-pass timing: HIP events recorded around each launch on the
@@ -293,8 +299,9 @@ static void free_tables(Tables<T>& t) {
 extern "C" void fe_plan_destroy(fe_plan* p) {
   if (!p) return;
   (void)hipSetDevice(p->device);
-  void* bufs[] = {p->eps_ws, p->R,      p->S,       p->partials, p->partials2, p->red, p->flag,
-                  p->coef,   p->coef64, p->dlt,     p->rfield,   p->dsig_hi,   p->d64, p->s64};
+  void* bufs[] = {p->eps_ws, p->R,      p->S,       p->partials, p->partials2, p->red,     p->flag,   p->coef,
+                  p->coef64, p->dlt,    p->rfield,  p->dsig_hi,  p->d64,       p->s64,     p->dlt_alt, p->eps_alt,
+                  p->R2};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_tables(p->t32);
@@ -500,6 +507,12 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
 
   T* R = static_cast<T*>(p->R);
   cpx<T>* S = static_cast<cpx<T>*>(p->S);
+  T* R2 = nullptr;  // displacement form: the fused update writes the next divergence here
+  if (p->displacement) {
+    if (!p->R2) HIP_TRY(dmalloc(p, &p->R2, 3 * (size_t)N * sizeof(T)));
+    if (!p->eps_alt) HIP_TRY(dmalloc(p, &p->eps_alt, 6 * (size_t)N * sizeof(T)));
+    R2 = static_cast<T*>(p->R2);
+  }
   const int ncomp = p->displacement ? 3 : 6;
   const int accel = p->scheme == FE_ACCELERATED;
   const int max_iter = p->opt.max_iter;
@@ -520,16 +533,33 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
   // and the anchor's strain residual rf and stress divergence dbase come from
   // float64 arithmetic.
   T* it = eps;
+  T* nxt = static_cast<T*>(p->eps_alt);  // the fused update writes the next iterate here, then they swap
   const T* rf = nullptr;
   const T* dbase = nullptr;
   double mean_hi[6] = {0, 0, 0, 0, 0, 0};
   bool anchored = false;
   int refinements = 0;
+  bool have_D = false;  // R holds the divergence of the current iterate and partials its sums
+  int nb_D = 0;
+  // without an anchor the strain must sit in eps before float64 work reads it
+  auto sync_iterate = [&]() -> fe_status {
+    if (!anchored && it != eps) {
+      HIP_TRY(hipMemcpyAsync(eps, it, 6 * (size_t)N * sizeof(T), hipMemcpyDeviceToDevice, s));
+      nxt = it;
+      it = eps;
+    }
+    return FE_OK;
+  };
 
   // float64 re-anchor at the strain eps (+ it if anchored)
   auto reanchor = [&]() -> fe_status {
     const size_t spec = (size_t)d.H * d.ny * d.nx;
+    {
+      fe_status ss = sync_iterate();
+      if (ss != FE_OK) return ss;
+    }
     if (!p->dlt) {
+      HIP_TRY(dmalloc(p, &p->dlt_alt, 6 * (size_t)N * sizeof(T)));
       HIP_TRY(dmalloc(p, &p->dlt, 6 * (size_t)N * sizeof(T)));
       HIP_TRY(dmalloc(p, &p->rfield, 6 * (size_t)N * sizeof(T)));
       HIP_TRY(dmalloc(p, &p->dsig_hi, 3 * (size_t)N * sizeof(T)));
@@ -552,14 +582,18 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     HIP_TRY(hipStreamSynchronize(s));
     for (int i = 0; i < 6; ++i) mean_hi[i] = p->h_red[1 + i] / (double)N;
     it = static_cast<T*>(p->dlt);
+    nxt = static_cast<T*>(p->dlt_alt);
     rf = static_cast<const T*>(p->rfield);
     dbase = static_cast<const T*>(p->dsig_hi);
     anchored = true;
+    have_D = false;
     ++refinements;
     return FE_OK;
   };
   // float64 eta of the strain eps (+ it if anchored), folding it into eps
   auto verify_total = [&](double* ev) -> fe_status {
+    fe_status ss = sync_iterate();
+    if (ss != FE_OK) return ss;
     if (anchored) {
       Launch<T>::axpy(eps, it, 6 * N, s);
       HIP_TRY(hipMemsetAsync(it, 0, 6 * (size_t)N * sizeof(T), s));
@@ -587,9 +621,11 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     }
     const bool check = (k % every == 0) || k == max_iter;
     if (p->displacement) {
-      int nb = 0;
-      tm.run(FE_PASS_POINTWISE, [&] { nb = Launch<T>::div(it, phase, coef, R, dbase, p->partials, d, p->op, s); });
-      if (check) tm.run(FE_PASS_ETA, [&] { launch_reduce(p->partials, nb, 7, p->red, s); });
+      if (!have_D) {
+        tm.run(FE_PASS_POINTWISE, [&] { nb_D = Launch<T>::div(it, phase, coef, R, dbase, p->partials, d, p->op, s); });
+        have_D = true;
+      }
+      if (check) tm.run(FE_PASS_ETA, [&] { launch_reduce(p->partials, nb_D, 7, p->red, s); });
     } else if (check) {
       tm.run(FE_PASS_ETA, [&] {
         Launch<T>::tau6(eps, phase, coef, R, 1, p->partials, p->div_blocks, d, s);
@@ -665,7 +701,13 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen3(S, d, tb.tw[0], wt, g, p->op, s); });
       tm.run(FE_PASS_YINV, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], 1, s); });
       tm.run(FE_PASS_ZINV, [&] { Launch<T>::zc2r(S, R, 3, d, tb.tw[2], s); });
-      tm.run(FE_PASS_UPDATE, [&] { Launch<T>::grad_update(R, it, phase, coef, g, rf, d, p->op, accel, s); });
+      // eps^(k+1) (into nxt) and the divergence of its tau (into R2) with eta's sums
+      tm.run(FE_PASS_UPDATE, [&] {
+        nb_D = Launch<T>::update_div(R, it, nxt, phase, coef, g, rf, R2, dbase, p->partials, d, p->op, accel, s);
+      });
+      std::swap(it, nxt);
+      std::swap(R, R2);
+      have_D = true;
     } else {
       tm.run(FE_PASS_POINTWISE, [&] { Launch<T>::tau6(eps, phase, coef, R, 0, nullptr, p->div_blocks, d, s); });
       tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 6, d, tb.tw[2], s); });
@@ -680,6 +722,9 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
   if (anchored) {  // the returned strain is anchor + correction
     Launch<T>::axpy(eps, it, 6 * N, s);
     HIP_TRY(hipMemsetAsync(it, 0, 6 * (size_t)N * sizeof(T), s));
+  } else {
+    fe_status ss = sync_iterate();
+    if (ss != FE_OK) return ss;
   }
   HIP_TRY(hipEventRecord(p->ev1, s));
   HIP_TRY(hipEventSynchronize(p->ev1));
@@ -776,8 +821,12 @@ struct BatchClass {
   std::vector<int> ids;  // sample indices of the batch in this class
   int ncoef = 1;
   int div_blocks = 0;
-  T* eps = nullptr;
+  T* eps = nullptr;   // returned strains (every retired sample's final iterate ends here)
+  T* eps2 = nullptr;  // second iterate buffer of the fused update
   T* R = nullptr;
+  T* R2 = nullptr;
+  T* cur = nullptr;   // current iterate buffer (eps or eps2)
+  T* nxt = nullptr;
   cpx<T>* S = nullptr;
   uint8_t* phase = nullptr;
   double* partials = nullptr;
@@ -795,7 +844,7 @@ struct BatchClass {
   std::vector<double> best;
   std::vector<int> best_k;
   void release() {
-    void* b[] = {eps, R, S, phase, partials, red, coef, coef64, gcon, active, all, tw[0], tw[1], tw[2],
+    void* b[] = {eps, eps2, R, R2, S, phase, partials, red, coef, coef64, gcon, active, all, tw[0], tw[1], tw[2],
                  wave[0], wave[1], wave[2]};
     for (void* x : b)
       if (x) (void)hipFree(x);
@@ -810,7 +859,11 @@ fe_status alloc_class(BatchClass<T>& c, int op) {
   const long long N = c.d.N;
   const size_t spec = (size_t)c.d.H * c.d.ny * c.d.nx;
   HIP_TRY(hipMalloc((void**)&c.eps, n * 6 * N * sizeof(T)));
+  HIP_TRY(hipMalloc((void**)&c.eps2, n * 6 * N * sizeof(T)));
   HIP_TRY(hipMalloc((void**)&c.R, n * 3 * N * sizeof(T)));
+  HIP_TRY(hipMalloc((void**)&c.R2, n * 3 * N * sizeof(T)));
+  c.cur = c.eps;
+  c.nxt = c.eps2;
   HIP_TRY(hipMalloc((void**)&c.S, n * 3 * spec * sizeof(cpx<T>)));
   HIP_TRY(hipMalloc((void**)&c.phase, n * N));
   HIP_TRY(hipMalloc((void**)&c.partials, n * (size_t)c.div_blocks * 7 * sizeof(double)));
@@ -931,17 +984,14 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, s));
   std::vector<double> hred;
+  // eta^0: divergence of eps_bar for every sample
+  for (auto& c : cls) {
+    const int na = (int)c.act.size();
+    const Batch bt{c.active, c.ncoef};
+    Launch<T>::div(c.cur, c.phase, c.coef, c.R, nullptr, c.partials, c.d, op, s, bt, na);
+    launch_reduce(c.partials, c.div_blocks, 7, c.red, s, c.active, na);
+  }
   for (int k = 0;; ++k) {
-    bool any = false;
-    for (auto& c : cls) {
-      const int na = (int)c.act.size();
-      if (!na) continue;
-      any = true;
-      const Batch bt{c.active, c.ncoef};
-      Launch<T>::div(c.eps, c.phase, c.coef, c.R, nullptr, c.partials, c.d, op, s, bt, na);
-      launch_reduce(c.partials, c.div_blocks, 7, c.red, s, c.active, na);
-    }
-    if (!any) break;
     HIP_TRY(hipStreamSynchronize(s));
     bool left = false;
     for (auto& c : cls) {
@@ -958,34 +1008,35 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
         out.iterations = k;
         out.eta = eta;
         for (int q = 0; q < 6; ++q) out.mean_stress[q] = mean[q];
+        bool done = true;
         // same stopping order as the single-sample solve
         if (!std::isfinite(eta)) {
           out.status = FE_DIVERGED;
-          continue;
-        }
-        if (eta <= tol) {
+        } else if (eta <= tol) {
           out.status = FE_OK;
-          continue;
-        }
-        if (k >= o.max_iter) {
+        } else if (k >= o.max_iter) {
           out.status = FE_NOT_CONVERGED;
-          continue;
+        } else {
+          c.rising[j] = eta > c.prev[j] ? c.rising[j] + 1 : 0;
+          c.prev[j] = eta;
+          if (o.diverge_window > 0 && c.rising[j] >= o.diverge_window) {
+            out.status = FE_DIVERGED;
+          } else if (eta < 0.95 * c.best[j]) {  // storage floor: no 5% gain over kStallWindow iterations
+            c.best[j] = eta;
+            c.best_k[j] = k;
+            done = false;
+          } else if (k - c.best_k[j] >= kStallWindow) {
+            out.status = FE_NOT_CONVERGED;
+          } else {
+            done = false;
+          }
         }
-        c.rising[j] = eta > c.prev[j] ? c.rising[j] + 1 : 0;
-        c.prev[j] = eta;
-        if (o.diverge_window > 0 && c.rising[j] >= o.diverge_window) {
-          out.status = FE_DIVERGED;
-          continue;
+        if (!done) {
+          keep.push_back(j);
+        } else if (c.cur != c.eps) {  // the final iterate goes to the returned buffer
+          HIP_TRY(hipMemcpyAsync(c.eps + (size_t)j * 6 * c.d.N, c.cur + (size_t)j * 6 * c.d.N,
+                                 6 * c.d.N * sizeof(T), hipMemcpyDeviceToDevice, s));
         }
-        // storage floor: no 5% gain over kStallWindow iterations
-        if (eta < 0.95 * c.best[j]) {
-          c.best[j] = eta;
-          c.best_k[j] = k;
-        } else if (k - c.best_k[j] >= kStallWindow) {
-          out.status = FE_NOT_CONVERGED;
-          continue;
-        }
-        keep.push_back(j);
       }
       c.act.swap(keep);  // c.act stays untouched until the next synchronisation
       if (!c.act.empty()) {
@@ -1006,7 +1057,11 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
       Launch<T>::xgreen3(c.S, c.d, c.tw[0], wt, g0, op, s, bt, c.gcon, na);
       Launch<T>::yfft(c.S, 3, c.d, c.tw[1], 1, s, bt, na);
       Launch<T>::zc2r(c.S, c.R, 3, c.d, c.tw[2], s, bt, na);
-      Launch<T>::grad_update(c.R, c.eps, c.phase, c.coef, g0, nullptr, c.d, op, accel, s, bt, c.gcon, na);
+      Launch<T>::update_div(c.R, c.cur, c.nxt, c.phase, c.coef, g0, nullptr, c.R2, nullptr, c.partials, c.d, op, accel,
+                            s, bt, c.gcon, na);
+      launch_reduce(c.partials, c.div_blocks, 7, c.red, s, c.active, na);
+      std::swap(c.cur, c.nxt);
+      std::swap(c.R, c.R2);
     }
     HIP_TRY(hipGetLastError());
   }

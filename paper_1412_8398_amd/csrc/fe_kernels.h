@@ -70,6 +70,13 @@ struct Launch {
   static void grad_update(const T* U, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef,
                           GreenConst<T> g, const T* rfield, Dims d, int op, int accelerated, hipStream_t s,
                           Batch bt = Batch{nullptr, 0}, const GreenConst<T>* gs = nullptr, int nsamp = 1);
+  // grad_update then div in one walk: eps_out = update(U, eps_in) and D = div tau(eps_out)
+  // with eta's partial sums; eps_in and eps_out must not overlap.  Returns the
+  // number of partial sums (same tiling as div).
+  static int update_div(const T* U, const T* eps_in, T* eps_out, const uint8_t* phase, const PhaseCoef<T>* coef,
+                        GreenConst<T> g, const T* rfield, T* D, const T* Dsig_base, double* partials, Dims d,
+                        int op, int accelerated, hipStream_t s, Batch bt = Batch{nullptr, 0},
+                        const GreenConst<T>* gs = nullptr, int nsamp = 1);
   static void axpy(T* y, const T* x, long long n, hipStream_t s);  // y += x
   static void xgreen3(cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> wt, GreenConst<T> g, int op,
                       hipStream_t s, Batch bt = Batch{nullptr, 0}, const GreenConst<T>* gs = nullptr, int nsamp = 1);
@@ -122,6 +129,6 @@ void launch_reduce(const double* partials, int nblocks, int nv, double* out, hip
                    const int* active = nullptr, int nsamp = 1);
 
 constexpr int kThreads = 256;
-constexpr int kMaxReduceBlocks = 4096;
+constexpr int kMaxReduceBlocks = 16384;
 
 }  // namespace fe

@@ -35,6 +35,57 @@ __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >=
 // periodic index for any i >= -n
 __device__ __forceinline__ int pmod(int i, int n) { return (i + n) % n; }
 
+// Strain of the iteration from the gradient gr[i][j] = d_i U_j: e = base +
+// sym(gr) (base = eps_bar, or the anchor's residual field); DS (eq. (9))
+// returns e, AS (eq. (16)) cur + 2 kappa0/(kappa+kappa0) sph(e - cur)
+// + 2 mu0/(mu+mu0) dev(e - cur).
+template <typename T, bool AS>
+__device__ __forceinline__ void strain_update(const T (&gr)[3][3], const T (&base)[6], const T (&cur)[6],
+                                              const PhaseCoef<T>& pc, T (&out)[6]) {
+  T e[6];
+  e[0] = base[0] + gr[0][0];
+  e[1] = base[1] + gr[1][1];
+  e[2] = base[2] + gr[2][2];
+  e[3] = base[3] + T(0.5) * (gr[1][2] + gr[2][1]);
+  e[4] = base[4] + T(0.5) * (gr[0][2] + gr[2][0]);
+  e[5] = base[5] + T(0.5) * (gr[0][1] + gr[1][0]);
+  if (AS) {
+    T dd[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) dd[k] = e[k] - cur[k];
+    const T sph = (dd[0] + dd[1] + dd[2]) * T(1.0 / 3.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[k] = cur[k] + pc.ak * sph + pc.am * (dd[k] - sph);
+#pragma unroll
+    for (int k = 3; k < 6; ++k) out[k] = cur[k] + pc.am * dd[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) out[k] = e[k];
+  }
+}
+
+// ROT gradient at a voxel from U at its 8 corners, u[a] with a = ax + 2 ay + 4 az:
+// d_i U_j = 1/4 sum_a s_i(a) U_j(v + a), s_i(a) = +1 if a_i = 1 else -1 (eq. (37)).
+template <typename T>
+__device__ __forceinline__ void grad_rot(const T (&u)[8][3], T (&gr)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gr[i][j] = T(0);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const T sg[3] = {(a & 1) ? T(1) : T(-1), (a & 2) ? T(1) : T(-1), (a & 4) ? T(1) : T(-1)};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) gr[i][j] += sg[i] * u[a][j];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gr[i][j] *= T(0.25);
+}
+
 // --------------------------------------------------------------------------
 // initialisation, checks, conversions
 // --------------------------------------------------------------------------
@@ -221,16 +272,241 @@ __global__ __launch_bounds__(DX * DY) void k_div(const TS* __restrict__ eps, con
   }
 }
 
+// --------------------------------------------------------------------------
+// fused strain update and divergence (WP, ROT): from U (the inverse transform
+// of iteration k) and eps^k, compute eps^(k+1) and, in the same walk along z,
+// the divergences of tau(eps^(k+1)) and sigma(eps^(k+1)) with eta's partial
+// sums -- the work of k_grad_update followed by k_div without writing eps^(k+1)
+// and reading it back.  Same tiles, walk and reductions as k_div.  The voxels
+// of the -x, -y halo are recomputed (their owner tile writes them), so eps^k
+// and eps^(k+1) must be different buffers.
+//   U plane z and z+1 in LDS (corners / voxels x0-1 .. x0+DX, y0-1 .. y0+DY),
+//   eps^(k+1), tau, sigma of voxel plane z (x0-1 .. x0+DX-1, y0-1 .. y0+DY-1).
+// --------------------------------------------------------------------------
+// Workgroup barrier that orders LDS accesses only: global loads issued before
+// it stay in flight (they prefetch the next plane).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <typename T, int OP, bool AS, bool RF>
+__global__ __launch_bounds__(DX * DY) void k_update_div(const T* __restrict__ U, const T* __restrict__ eps_in,
+                                                        T* __restrict__ eps_out, const uint8_t* __restrict__ phase,
+                                                        const PhaseCoef<T>* __restrict__ coef, int ncoef,
+                                                        GreenConst<T> g, const T* __restrict__ rfield,
+                                                        T* __restrict__ Dtau, const T* __restrict__ Dsig_base,
+                                                        double* __restrict__ partials, Dims d, int zchunk, Batch bt,
+                                                        const GreenConst<T>* __restrict__ gs) {
+  const long long N = d.N;
+  {
+    const long long smp = bt.active ? bt.active[blockIdx.y] : 0;
+    U += smp * 3 * N;
+    eps_in += smp * 6 * N;
+    eps_out += smp * 6 * N;
+    phase += smp * N;
+    coef += smp * bt.ncoef;
+    if (RF) rfield += smp * 6 * N;
+    Dtau += smp * 3 * N;
+    if (Dsig_base) Dsig_base += smp * 3 * N;
+    partials += smp * gridDim.x * 7;
+    if (gs) g = gs[smp];
+  }
+  constexpr int UR = (DX + 2) * (DY + 2), ER = (DX + 1) * (DY + 1), NT = DX * DY;
+  constexpr int US = (UR + NT - 1) / NT, ES = (ER + NT - 1) / NT;  // per-thread slots
+  __shared__ T su[2][3][DY + 2][DX + 2];  // component-major: consecutive lanes hit consecutive banks
+  __shared__ T st[6][DY + 1][DX + 1];
+  __shared__ T ss[6][DY + 1][DX + 1];
+  __shared__ PhaseCoef<T> sc[256];
+  __shared__ double red[7 * 16];
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const int ntx = (nx + DX - 1) / DX, nty = (ny + DY - 1) / DY;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int bx = tile % ntx;
+  const int rest = tile / ntx;
+  const int by = rest % nty;
+  const int bz = rest / nty;
+  const int x0 = bx * DX, y0 = by * DY, z0 = bz * zchunk;
+  const int z1 = min(nz, z0 + zchunk);
+  const int tx = threadIdx.x % DX, ty = threadIdx.x / DX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool own = x < nx && y < ny;
+  for (int i = threadIdx.x; i < ncoef; i += NT) sc[i] = coef[i];
+
+  // register prefetch of the next planes: U (corners), eps^k and phase (voxels)
+  T ureg[US][3];
+  T ereg[ES][6];
+  int preg[ES];
+  auto fetch_u = [&](int zz) {
+    const int z = pmod(zz, nz);
+#pragma unroll
+    for (int q = 0; q < US; ++q) {
+      const int idx = threadIdx.x + q * NT;
+      if (idx < UR) {
+        const int i = idx % (DX + 2), j = idx / (DX + 2);
+        const long long c = ((long long)z * ny + pmod(y0 - 1 + j, ny)) * nx + pmod(x0 - 1 + i, nx);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ureg[q][k] = U[k * N + c];
+      }
+    }
+  };
+  auto store_u = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < US; ++q) {
+      const int idx = threadIdx.x + q * NT;
+      if (idx < UR) {
+        const int i = idx % (DX + 2), j = idx / (DX + 2);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) su[buf][k][j][i] = ureg[q][k];
+      }
+    }
+  };
+  auto fetch_e = [&](int zz) {
+    const int z = pmod(zz, nz);
+#pragma unroll
+    for (int q = 0; q < ES; ++q) {
+      const int idx = threadIdx.x + q * NT;
+      if (idx < ER) {
+        const int i = idx % (DX + 1), j = idx / (DX + 1);
+        const long long v = ((long long)z * ny + pmod(y0 - 1 + j, ny)) * nx + pmod(x0 - 1 + i, nx);
+        preg[q] = phase[v];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ereg[q][k] = AS ? eps_in[k * N + v] : T(0);
+      }
+    }
+  };
+
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  T pt[3] = {0, 0, 0}, qt[3] = {0, 0, 0}, ps[3] = {0, 0, 0}, qs[3] = {0, 0, 0};
+  fetch_u(z0 - 1);
+  store_u(0);
+  fetch_u(z0);
+  fetch_e(z0 - 1);
+  for (int zz = z0 - 1; zz < z1; ++zz) {
+    const int b = (zz - z0 + 1) & 1;  // su[b]: plane zz, su[b ^ 1]: plane zz + 1
+    store_u(b ^ 1);
+    if (zz + 1 < z1) fetch_u(zz + 2);  // in flight during this plane's update
+    lds_barrier();
+    const int z = zz < 0 ? zz + nz : zz;
+#pragma unroll
+    for (int q = 0; q < ES; ++q) {
+      const int idx = threadIdx.x + q * NT;
+      if (idx >= ER) continue;
+      const int i = idx % (DX + 1), j = idx / (DX + 1);
+      const int xg = x0 - 1 + i, yg = y0 - 1 + j;
+      const long long v = ((long long)z * ny + pmod(yg, ny)) * nx + pmod(xg, nx);
+      T gr[3][3];
+      if (OP == OP_ROT) {
+        T u[8][3];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) u[a][k] = su[b ^ (a >> 2)][k][j + ((a >> 1) & 1)][i + (a & 1)];
+        grad_rot(u, gr);
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+          const T u0 = su[b][jj][j][i];
+          gr[0][jj] = su[b][jj][j][i + 1] - u0;
+          gr[1][jj] = su[b][jj][j + 1][i] - u0;
+          gr[2][jj] = su[b ^ 1][jj][j][i] - u0;
+        }
+      }
+      T base[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) base[k] = RF ? rfield[k * N + v] : g.macro[k];
+      const PhaseCoef<T> pc = sc[preg[q]];
+      T e[6];
+      strain_update<T, AS>(gr, base, ereg[q], pc, e);
+      if (i >= 1 && j >= 1 && xg < nx && yg < ny && zz >= z0)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) eps_out[k * N + v] = e[k];
+      T t[6], sg[6];
+      iso_apply(pc.dlam, pc.dmu, e, t);
+      iso_apply(pc.lam, pc.mu, e, sg);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        st[k][j][i] = t[k];
+        ss[k][j][i] = sg[k];
+      }
+    }
+    if (zz + 1 < z1) fetch_e(zz + 1);  // in flight during the divergence and the next store
+    lds_barrier();
+    T Pt[3], Qt[3], Ps[3], Qs[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int cx = voigt_of(0, j), cy = voigt_of(1, j), cz = voigt_of(2, j);
+      if (OP == OP_ROT) {
+        const T ax0 = st[cx][ty + 1][tx + 1], ax1 = st[cx][ty + 1][tx], ax2 = st[cx][ty][tx + 1], ax3 = st[cx][ty][tx];
+        const T ay0 = st[cy][ty + 1][tx + 1], ay1 = st[cy][ty + 1][tx], ay2 = st[cy][ty][tx + 1], ay3 = st[cy][ty][tx];
+        const T az0 = st[cz][ty + 1][tx + 1], az1 = st[cz][ty + 1][tx], az2 = st[cz][ty][tx + 1], az3 = st[cz][ty][tx];
+        Pt[j] = T(0.25) * (((ax1 + ax3) - (ax0 + ax2)) + ((ay2 + ay3) - (ay0 + ay1)));
+        Qt[j] = T(0.25) * ((az0 + az1) + (az2 + az3));
+        const T bx0 = ss[cx][ty + 1][tx + 1], bx1 = ss[cx][ty + 1][tx], bx2 = ss[cx][ty][tx + 1], bx3 = ss[cx][ty][tx];
+        const T by0 = ss[cy][ty + 1][tx + 1], by1 = ss[cy][ty + 1][tx], by2 = ss[cy][ty][tx + 1], by3 = ss[cy][ty][tx];
+        const T bz0 = ss[cz][ty + 1][tx + 1], bz1 = ss[cz][ty + 1][tx], bz2 = ss[cz][ty][tx + 1], bz3 = ss[cz][ty][tx];
+        Ps[j] = T(0.25) * (((bx1 + bx3) - (bx0 + bx2)) + ((by2 + by3) - (by0 + by1)));
+        Qs[j] = T(0.25) * ((bz0 + bz1) + (bz2 + bz3));
+      } else {
+        Pt[j] = (st[cx][ty + 1][tx + 1] - st[cx][ty + 1][tx]) + (st[cy][ty + 1][tx + 1] - st[cy][ty][tx + 1]);
+        Qt[j] = st[cz][ty + 1][tx + 1];
+        Ps[j] = (ss[cx][ty + 1][tx + 1] - ss[cx][ty + 1][tx]) + (ss[cy][ty + 1][tx + 1] - ss[cy][ty][tx + 1]);
+        Qs[j] = ss[cz][ty + 1][tx + 1];
+      }
+    }
+    if (zz >= z0 && own) {
+      const long long c = ((long long)z * ny + y) * nx + x;
+      T Dt[3], Ds[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if (OP == OP_ROT) {
+          Dt[j] = (Pt[j] + pt[j]) + (qt[j] - Qt[j]);
+          Ds[j] = (Ps[j] + ps[j]) + (qs[j] - Qs[j]);
+        } else {
+          Dt[j] = Pt[j] + (Qt[j] - qt[j]);
+          Ds[j] = Ps[j] + (Qs[j] - qs[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Dtau[j * N + c] = Dt[j];
+      double qd[3] = {double(Ds[0]), double(Ds[1]), double(Ds[2])};
+      if (Dsig_base) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) qd[j] += double(Dsig_base[j * N + c]);
+      }
+      acc[0] += qd[0] * qd[0] + qd[1] * qd[1] + qd[2] * qd[2];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[1 + k] += double(ss[k][ty + 1][tx + 1]);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      pt[j] = Pt[j];
+      qt[j] = Qt[j];
+      ps[j] = Ps[j];
+      qs[j] = Qs[j];
+    }
+    // st/ss are rewritten after the next step's first barrier, su[b] after this
+    // step's second: no third barrier needed
+  }
+  __syncthreads();
+  block_sum<7>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) partials[blockIdx.x * 7 + i] = acc[i];
+  }
+}
+
 // Tiling of the divergence walk: DX x DY corner tiles, z cut into chunks so
-// that there are at least 2048 workgroups (at most 4096 partial sums).
+// that there are about 8192 workgroups (at most 16384 partial sums).
 struct DivGrid {
   int blocks, zchunk;
 };
 static DivGrid div_grid(const Dims& d) {
   const int ntx = (d.nx + DX - 1) / DX, nty = (d.ny + DY - 1) / DY;
   const int bxy = ntx * nty;
-  int nch = (2048 + bxy - 1) / bxy;
-  if (nch > d.nz) nch = d.nz;
+  int nch = (8192 + bxy - 1) / bxy;  // several waves of resident workgroups
+  if (nch > d.nz / 8) nch = d.nz / 8;  // chunks of at least 8 planes (one halo plane each)
   if (nch < 1) nch = 1;
   const int zchunk = (d.nz + nch - 1) / nch;
   nch = (d.nz + zchunk - 1) / zchunk;
@@ -274,26 +550,16 @@ __global__ __launch_bounds__(256) void k_grad_update(const T* __restrict__ U, T*
     const int y = (int)((v / nx) % ny);
     const int z = (int)(v / ((long long)nx * ny));
     T gr[3][3];  // gr[i][j] = d_i U_j
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) gr[i][j] = T(0);
     if (OP == OP_ROT) {
+      T u[8][3];
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-        const long long c = ((long long)wrap(z + az, nz) * ny + wrap(y + ay, ny)) * nx + wrap(x + ax, nx);
-        const T u[3] = {U[c], U[N + c], U[2 * N + c]};
-        const T sg[3] = {ax ? T(1) : T(-1), ay ? T(1) : T(-1), az ? T(1) : T(-1)};
+        const long long c = ((long long)wrap(z + (a >> 2), nz) * ny + wrap(y + ((a >> 1) & 1), ny)) * nx +
+                            wrap(x + (a & 1), nx);
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j) gr[i][j] += sg[i] * u[j];
+        for (int k = 0; k < 3; ++k) u[a][k] = U[k * N + c];
       }
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) gr[i][j] *= T(0.25);
+      grad_rot(u, gr);
     } else {
       const T u0[3] = {U[v], U[N + v], U[2 * N + v]};
 #pragma unroll
@@ -306,33 +572,17 @@ __global__ __launch_bounds__(256) void k_grad_update(const T* __restrict__ U, T*
         for (int j = 0; j < 3; ++j) gr[i][j] = U[j * N + c] - u0[j];
       }
     }
-    T base[6];
+    T base[6], cur[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) base[k] = rfield ? rfield[k * N + v] : g.macro[k];
-    T e[6];
-    e[0] = base[0] + gr[0][0];
-    e[1] = base[1] + gr[1][1];
-    e[2] = base[2] + gr[2][2];
-    e[3] = base[3] + T(0.5) * (gr[1][2] + gr[2][1]);
-    e[4] = base[4] + T(0.5) * (gr[0][2] + gr[2][0]);
-    e[5] = base[5] + T(0.5) * (gr[0][1] + gr[1][0]);
-    if (AS) {
-      const PhaseCoef<T> pc = coef[phase[v]];
-      T cur[6], dd[6];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        cur[k] = eps[k * N + v];
-        dd[k] = e[k] - cur[k];
-      }
-      const T sph = (dd[0] + dd[1] + dd[2]) * T(1.0 / 3.0);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) eps[k * N + v] = cur[k] + pc.ak * sph + pc.am * (dd[k] - sph);
-#pragma unroll
-      for (int k = 3; k < 6; ++k) eps[k * N + v] = cur[k] + pc.am * dd[k];
-    } else {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) eps[k * N + v] = e[k];
+    for (int k = 0; k < 6; ++k) {
+      base[k] = rfield ? rfield[k * N + v] : g.macro[k];
+      cur[k] = AS ? eps[k * N + v] : T(0);
     }
+    const PhaseCoef<T> pc = coef[phase[v]];
+    T e[6];
+    strain_update<T, AS>(gr, base, cur, pc, e);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) eps[k * N + v] = e[k];
   }
 }
 
@@ -522,6 +772,38 @@ int Launch<T>::div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef,
   return gd.blocks;
 }
 
+template <typename T>
+int Launch<T>::update_div(const T* U, const T* eps_in, T* eps_out, const uint8_t* phase, const PhaseCoef<T>* coef,
+                          GreenConst<T> g, const T* rfield, T* D, const T* Dsig_base, double* partials, Dims d, int op,
+                          int accelerated, hipStream_t s, Batch bt, const GreenConst<T>* gs, int nsamp) {
+  const DivGrid gd = div_grid(d);
+  const dim3 grid(gd.blocks, nsamp), block(DX * DY);
+  // phase constants staged in LDS: a sample's table (batched) or the plan's 256 entries
+  const int ncoef = bt.active ? (bt.ncoef < 256 ? bt.ncoef : 256) : 256;
+#define FE_UD(OPV, ASV)                                                                                          \
+  do {                                                                                                             \
+    if (rfield)                                                                                                    \
+      hipLaunchKernelGGL((k_update_div<T, OPV, ASV, true>), grid, block, 0, s, U, eps_in, eps_out, phase, coef,    \
+                         ncoef, g, rfield, D, Dsig_base, partials, d, gd.zchunk, bt, gs);                          \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_update_div<T, OPV, ASV, false>), grid, block, 0, s, U, eps_in, eps_out, phase, coef,   \
+                         ncoef, g, rfield, D, Dsig_base, partials, d, gd.zchunk, bt, gs);                          \
+  } while (0)
+  if (op == OP_ROT) {
+    if (accelerated)
+      FE_UD(OP_ROT, true);
+    else
+      FE_UD(OP_ROT, false);
+  } else {
+    if (accelerated)
+      FE_UD(OP_WP, true);
+    else
+      FE_UD(OP_WP, false);
+  }
+#undef FE_UD
+  return gd.blocks;
+}
+
 template <typename TS>
 int launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* partials, Dims d,
                       int op, hipStream_t s) {
@@ -610,6 +892,9 @@ void launch_reduce(const double* partials, int nblocks, int nv, double* out, hip
   template int Launch<T>::div(const T*, const uint8_t*, const PhaseCoef<T>*, T*, const T*, double*, Dims, int, \
                               hipStream_t, Batch, int);                                                   \
   template void Launch<T>::axpy(T*, const T*, long long, hipStream_t);                                     \
+  template int Launch<T>::update_div(const T*, const T*, T*, const uint8_t*, const PhaseCoef<T>*, GreenConst<T>, \
+                                     const T*, T*, const T*, double*, Dims, int, int, hipStream_t, Batch,         \
+                                     const GreenConst<T>*, int);                                                  \
   template void Launch<T>::grad_update(const T*, T*, const uint8_t*, const PhaseCoef<T>*, GreenConst<T>,  \
                                        const T*, Dims, int, int, hipStream_t, Batch, const GreenConst<T>*, \
                                        int);                                                              \
