@@ -99,7 +99,7 @@ constexpr bool plan_ok(int N, int E) { return N % E == 0 && plan_ns(N, E, plan_s
 //  strided passes: up to 32 (2^a) or 24 (3*2^a)
 //  x passes: up to 16 (2^a) or 12 (3*2^a) with 3 components, 8 / 12 with 6
 constexpr int e_strided(int N) { return N % 3 == 0 ? (N >= 24 ? 24 : N) : (N >= 32 ? 32 : N); }
-constexpr int e_x3(int N) { return N % 3 == 0 ? (N >= 12 ? 12 : N) : (N >= 16 ? 16 : N); }
+constexpr int e_x3(int N) { return N % 3 == 0 ? (N >= 12 ? 12 : N) : (N >= 8 ? 8 : N); }
 constexpr int e_x6(int N) { return N % 3 == 0 ? (N >= 12 ? 12 : N) : (N >= 8 ? 8 : N); }
 
 // One Stockham stage over NC components held in registers.  `Lds` maps

@@ -109,7 +109,11 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __rest
   for (int m = 0; m < C::E; ++m) lds[(t + m * C::P) * C::TX + col] = v[0][m];
   __syncthreads();
   cpx2<T>* dst = reinterpret_cast<cpx2<T>*>(S + (long long)c * d.H * plane + (long long)y * d.nx + 2 * (ok ? pp : 0));
-  for (int mz = t; mz < d.H; mz += C::P) {
+  constexpr int H = N / 2 + 1, NS = (H + C::P - 1) / C::P;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int mz = t + i * C::P;
+    if (mz >= H) break;
     const cpx<T> Z = lds[mz * C::TX + col];
     const cpx<T> Zm = conj(lds[((N - mz) % N) * C::TX + col]);
     const cpx<T> Dd = sub(Z, Zm);
