@@ -275,6 +275,71 @@ def voronoi_cells(shape, n_seeds: int, n_phases: int, seed: int):
     return out, seeds, cell_phase
 
 
+def voronoi_cells_fast(shape, n_seeds: int, n_phases: int, seed: int, workers: int = -1):
+    """The tessellation of ``voronoi_cells`` (same seeds, same phases) labelled
+    with a periodic k-d tree (scipy.spatial.cKDTree, boxsize = the cell) plane
+    by plane: for grids of 10^9 voxels.  Exact ties between seeds (probability
+    zero for continuous seed positions) may resolve to another index than the
+    brute-force version's lowest one."""
+    from scipy.spatial import cKDTree
+
+    nz, ny, nx = shape
+    rng = SplitMix64(seed)
+    seeds = rng.uniform_array(3 * n_seeds).reshape(n_seeds, 3) * np.array([nx, ny, nz], dtype=np.float64)
+    cell_phase = np.array([rng.randint(n_phases) for _ in range(n_seeds)], dtype=np.uint8)
+    box = np.array([nx, ny, nz], dtype=np.float64)
+    tree = cKDTree(np.mod(seeds, box), boxsize=box)
+    out = np.empty(shape, dtype=np.uint8)
+    xs = np.arange(nx) + 0.5
+    ys = np.arange(ny) + 0.5
+    gx, gy = np.meshgrid(xs, ys)
+    pts = np.empty((ny * nx, 3))
+    pts[:, 0] = gx.reshape(-1)
+    pts[:, 1] = gy.reshape(-1)
+    for z in range(nz):
+        pts[:, 2] = z + 0.5
+        _, lab = tree.query(pts, k=1, workers=workers)
+        out[z] = cell_phase[lab].reshape(ny, nx)
+    return out, seeds, cell_phase
+
+
+def voronoi_cells_torch(shape, n_seeds: int, n_phases: int, seed: int, device="cuda", rows=16, progress=None):
+    """``voronoi_cells`` evaluated with torch on ``device``: the same float64
+    minimum-image squares dz^2, dy^2, dx^2 (precomputed per axis) summed in the
+    same order, argmin keeping the first of equal distances (the lowest seed
+    index).  ``rows`` y-rows are labelled per step; ``progress(z)`` (optional)
+    is called after each plane.  Returns a uint8 tensor on ``device`` and the
+    seeds and phases."""
+    import torch
+
+    nz, ny, nx = shape
+    rng = SplitMix64(seed)
+    seeds = np.empty((n_seeds, 3))
+    for s in range(n_seeds):
+        seeds[s, 0] = rng.uniform() * nx
+        seeds[s, 1] = rng.uniform() * ny
+        seeds[s, 2] = rng.uniform() * nz
+    cell_phase = np.array([rng.randint(n_phases) for _ in range(n_seeds)], dtype=np.uint8)
+    sd = torch.from_numpy(seeds).to(device)
+    cp = torch.from_numpy(cell_phase).to(device)
+
+    def sq(n, col):
+        d = (torch.arange(n, device=device, dtype=torch.float64) + 0.5)[:, None] - sd[None, :, col]
+        d = d - n * torch.round(d / n)
+        return d * d
+
+    dx2, dy2, dz2 = sq(nx, 0), sq(ny, 1), sq(nz, 2)  # (n, seeds)
+    out = torch.empty((nz, ny, nx), dtype=torch.uint8, device=device)
+    for z in range(nz):
+        for a in range(0, ny, rows):
+            zy = dz2[z][None, :] + dy2[a:a + rows]            # (rows, seeds)
+            d2 = zy[:, None, :] + dx2[None, :, :]               # (rows, nx, seeds)
+            out[z, a:a + rows] = cp[torch.argmin(d2, dim=2)]
+        if progress is not None:
+            progress(z)
+    return out, seeds, cell_phase
+
+
 def laminate(shape, layer_labels_along_x) -> np.ndarray:
     """Phase depends on the x index only: ``layer_labels_along_x[i]`` for every
     voxel with x index i."""

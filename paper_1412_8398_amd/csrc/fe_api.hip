@@ -609,12 +609,16 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
   const int W = 10;
   std::vector<double> hist;
   int rising = 0, k = 0, last_anchor = 0;
+  int anchor_gap = 2 * W;  // iterations between stagnation re-anchors; doubles after each (slow but steady runs)
+  double best = INFINITY;  // float32 without re-anchoring: best eta and where it was reached
+  int best_k = 0;
   bool need_anchor = false;
   for (k = 0;; ++k) {
     if (need_anchor) {
       fe_status rs = reanchor();
       if (rs != FE_OK) return rs;
       need_anchor = false;
+      if (refinements > 1) anchor_gap = std::min(2 * anchor_gap, 200);
       last_anchor = k;
       rising = 0;
       prev_eta = INFINITY;
@@ -688,8 +692,18 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       }
       // stagnation of the float32 iteration: less than 30% decrease over W checks
       const int nh = (int)hist.size();
-      if (can_refine && !need_anchor && k - last_anchor >= 2 * W && nh > W && eta > 0.7 * hist[nh - 1 - W])
+      if (can_refine && !need_anchor && k - last_anchor >= anchor_gap && nh > W && eta > 0.7 * hist[nh - 1 - W])
         need_anchor = true;
+      // float32 without re-anchoring: stop at the storage floor (no 5% gain in 100 iterations)
+      if (!can_refine && sizeof(T) == 4) {
+        if (eta < 0.95 * best) {
+          best = eta;
+          best_k = k;
+        } else if (k - best_k >= 100) {
+          status = FE_NOT_CONVERGED;
+          break;
+        }
+      }
       if (can_refine && p->opt.diverge_window > 0 && rising >= p->opt.diverge_window && refinements > 3) {
         status = FE_DIVERGED;
         break;

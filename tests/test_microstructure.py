@@ -34,3 +34,24 @@ def test_uniform_array_and_poisson_fast_consume_the_same_sequence():
     for mean in (0.5, 7.0, 300.0, 5000.0):
         assert a.poisson_fast(mean) == b.poisson(mean)
         assert a.state == b.state
+
+
+@pytest.mark.parametrize("shape,n,seed", [((16, 12, 20), 30, 4), ((24, 24, 24), 64, 9), ((8, 32, 16), 5, 1)])
+def test_kd_tree_voronoi_equals_the_brute_force_labelling(shape, n, seed):
+    from microstructure import voronoi_cells, voronoi_cells_fast
+
+    a, sa, pa = voronoi_cells(shape, n, 3, seed)
+    b, sb, pb = voronoi_cells_fast(shape, n, 3, seed, workers=1)
+    assert np.array_equal(sa, sb) and np.array_equal(pa, pb)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("shape,n,seed", [((16, 12, 20), 30, 4), ((12, 8, 16), 7, 2)])
+def test_torch_voronoi_equals_the_brute_force_labelling(shape, n, seed):
+    torch = pytest.importorskip("torch")
+    from microstructure import voronoi_cells, voronoi_cells_torch
+
+    a, sa, pa = voronoi_cells(shape, n, 3, seed)
+    b, sb, pb = voronoi_cells_torch(shape, n, 3, seed, device="cpu", rows=5)
+    assert np.array_equal(sa, sb) and np.array_equal(pa, pb)
+    assert np.array_equal(a, b.numpy())
