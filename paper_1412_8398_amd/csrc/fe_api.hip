@@ -112,7 +112,8 @@ struct fe_plan {
   Tables<double> t64;
   size_t ws_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipEvent_t tev[64] = {};  // pass timing pool (pairs)
+  hipEvent_t evc = nullptr;  // recorded after eta's copy to the host (the next passes run meanwhile)
+  hipEvent_t tev[512] = {};  // pass timing pool (pairs)
   // mixed-precision refinement workspace (allocated on first use)
   void* dlt = nullptr;       // correction, 6 planes (plan precision)
   void* rfield = nullptr;    // strain residual of the anchor, 6 planes
@@ -131,7 +132,8 @@ struct PassTimer {
   fe_plan* p;
   bool on;
   int used = 0;
-  int pass_of[32];
+  static constexpr int kSlots = 256;
+  int pass_of[kSlots];
   double sec[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   PassTimer(fe_plan* plan, bool enabled) : p(plan), on(enabled) {}
@@ -141,7 +143,7 @@ struct PassTimer {
       f();
       return;
     }
-    if (used == 32) flush();
+    if (used == kSlots) flush();
     (void)hipEventRecord(p->tev[2 * used], p->stream);
     f();
     (void)hipEventRecord(p->tev[2 * used + 1], p->stream);
@@ -279,10 +281,11 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
     return cleanup_fail(fail(FE_ERR_DEVICE, "pinned host buffer"));
   if ((st = upload_tables<float>(p, p->t32)) != FE_OK) return cleanup_fail(st);
   if ((st = upload_tables<double>(p, p->t64)) != FE_OK) return cleanup_fail(st);
-  if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
+  if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess ||
+      hipEventCreateWithFlags(&p->evc, hipEventDisableTiming) != hipSuccess)
     return cleanup_fail(fail(FE_ERR_DEVICE, "event creation"));
   if (o.timing)
-    for (int i = 0; i < 64; ++i)
+    for (int i = 0; i < 512; ++i)
       if (hipEventCreate(&p->tev[i]) != hipSuccess) return cleanup_fail(fail(FE_ERR_DEVICE, "event creation"));
   *out = p;
   return FE_OK;
@@ -309,6 +312,7 @@ extern "C" void fe_plan_destroy(fe_plan* p) {
   if (p->h_red) (void)hipHostFree(p->h_red);
   if (p->ev0) (void)hipEventDestroy(p->ev0);
   if (p->ev1) (void)hipEventDestroy(p->ev1);
+  if (p->evc) (void)hipEventDestroy(p->evc);
   for (hipEvent_t e : p->tev)
     if (e) (void)hipEventDestroy(e);
   delete p;
@@ -640,10 +644,33 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
         launch_reduce(p->partials2, xblk, 1, p->red + 8, s);
       });
     }
+    // Displacement form: the passes of iteration k are queued before eta^k is
+    // read back, so the GPU works while the host decides.  They write only
+    // nxt, R (the displacement), R2 and the partial sums, never it: when the
+    // check stops, re-anchors or verifies (which may move it), the queued
+    // iteration is dropped and the divergence of it is recomputed.
+    bool queued = false, dropped = false;
+    auto enqueue_passes = [&]() {
+      tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 3, d, tb.tw[2], s); });
+      tm.run(FE_PASS_YFWD, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], 0, s); });
+      tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen3(S, d, tb.tw[0], wt, g, p->op, s); });
+      tm.run(FE_PASS_YINV, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], 1, s); });
+      tm.run(FE_PASS_ZINV, [&] { Launch<T>::zc2r(S, R, 3, d, tb.tw[2], s); });
+      // eps^(k+1) (into nxt) and the divergence of its tau (into R2) with eta's sums
+      tm.run(FE_PASS_UPDATE, [&] {
+        nb_D = Launch<T>::update_div(R, it, nxt, phase, coef, g, rf, R2, dbase, p->partials, d, p->op, accel, s);
+      });
+    };
     if (check) {
       HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      tm.flush();
+      if (p->displacement && k < max_iter) {
+        HIP_TRY(hipEventRecord(p->evc, s));
+        enqueue_passes();
+        queued = true;
+        HIP_TRY(hipEventSynchronize(p->evc));
+      } else {
+        HIP_TRY(hipStreamSynchronize(s));
+      }
       for (int i = 0; i < 6; ++i) mean[i] = mean_hi[i] + p->h_red[1 + i] / (double)N;
       const double nrm = frob(mean);
       eta = p->displacement ? std::sqrt(p->h_red[0] / (double)N) / nrm : std::sqrt(p->h_red[8]) / ((double)N * nrm);
@@ -659,6 +686,7 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
           break;
         }
         // the float32 measure says converged: confirm in float64
+        dropped = true;
         fe_status vs = verify_total(&verified);
         if (vs != FE_OK) return vs;
         if (verified <= tol) {
@@ -710,18 +738,14 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       }
     }
     if (p->displacement) {
-      tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 3, d, tb.tw[2], s); });
-      tm.run(FE_PASS_YFWD, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], 0, s); });
-      tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen3(S, d, tb.tw[0], wt, g, p->op, s); });
-      tm.run(FE_PASS_YINV, [&] { Launch<T>::yfft(S, 3, d, tb.tw[1], 1, s); });
-      tm.run(FE_PASS_ZINV, [&] { Launch<T>::zc2r(S, R, 3, d, tb.tw[2], s); });
-      // eps^(k+1) (into nxt) and the divergence of its tau (into R2) with eta's sums
-      tm.run(FE_PASS_UPDATE, [&] {
-        nb_D = Launch<T>::update_div(R, it, nxt, phase, coef, g, rf, R2, dbase, p->partials, d, p->op, accel, s);
-      });
-      std::swap(it, nxt);
-      std::swap(R, R2);
-      have_D = true;
+      if (!queued && !dropped) enqueue_passes();
+      if (dropped) {
+        have_D = false;  // R holds a displacement now; the divergence of it is recomputed
+      } else {
+        std::swap(it, nxt);
+        std::swap(R, R2);
+        have_D = true;
+      }
     } else {
       tm.run(FE_PASS_POINTWISE, [&] { Launch<T>::tau6(eps, phase, coef, R, 0, nullptr, p->div_blocks, d, s); });
       tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 6, d, tb.tw[2], s); });
@@ -1002,8 +1026,8 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
   for (auto& c : cls) {
     const int na = (int)c.act.size();
     const Batch bt{c.active, c.ncoef};
-    Launch<T>::div(c.cur, c.phase, c.coef, c.R, nullptr, c.partials, c.d, op, s, bt, na);
-    launch_reduce(c.partials, c.div_blocks, 7, c.red, s, c.active, na);
+    const int nb = Launch<T>::div(c.cur, c.phase, c.coef, c.R, nullptr, c.partials, c.d, op, s, bt, na);
+    launch_reduce(c.partials, nb, 7, c.red, s, c.active, na);
   }
   for (int k = 0;; ++k) {
     HIP_TRY(hipStreamSynchronize(s));
@@ -1071,9 +1095,9 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
       Launch<T>::xgreen3(c.S, c.d, c.tw[0], wt, g0, op, s, bt, c.gcon, na);
       Launch<T>::yfft(c.S, 3, c.d, c.tw[1], 1, s, bt, na);
       Launch<T>::zc2r(c.S, c.R, 3, c.d, c.tw[2], s, bt, na);
-      Launch<T>::update_div(c.R, c.cur, c.nxt, c.phase, c.coef, g0, nullptr, c.R2, nullptr, c.partials, c.d, op, accel,
-                            s, bt, c.gcon, na);
-      launch_reduce(c.partials, c.div_blocks, 7, c.red, s, c.active, na);
+      const int nb = Launch<T>::update_div(c.R, c.cur, c.nxt, c.phase, c.coef, g0, nullptr, c.R2, nullptr, c.partials,
+                                           c.d, op, accel, s, bt, c.gcon, na);
+      launch_reduce(c.partials, nb, 7, c.red, s, c.active, na);
       std::swap(c.cur, c.nxt);
       std::swap(c.R, c.R2);
     }
@@ -1091,8 +1115,8 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
   for (auto& c : cls) {
     const int n = (int)c.ids.size();
     const Batch bt{c.all, c.ncoef};
-    launch_div64<T>(c.eps, c.phase, c.coef64, nullptr, nullptr, c.partials, c.d, op, s, bt, n);
-    launch_reduce(c.partials, c.div_blocks, 7, c.red, s, c.all, n);
+    const int nb = launch_div64<T>(c.eps, c.phase, c.coef64, nullptr, nullptr, c.partials, c.d, op, s, bt, n);
+    launch_reduce(c.partials, nb, 7, c.red, s, c.all, n);
     hred.resize((size_t)n * 8);
     HIP_TRY(hipMemcpyAsync(hred.data(), c.red, hred.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -120,7 +120,8 @@ int launch_div64(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* c
 template <typename TE>
 void launch_residual(const double* U, const TE* eps, GreenConst<double> g, TE* r, Dims d, int op, hipStream_t s);
 
-// Number of partial sums (per sample) a divergence launch over grid d writes.
+// Upper bound on the partial sums (per sample) a divergence launch over grid d
+// writes, float or double tiles; the launchers return the exact count.
 int div_partial_count(Dims d);
 
 // Fixed-order sums of per-block partials: out[8*sample + i] for i < nv; with an

@@ -56,8 +56,9 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_ypass(cpx<T>* __rest
   __shared__ cpx<T> lds[N * C::TX];
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
   const int ntx = (d.nx + C::TX - 1) / C::TX;
-  const int xt = blockIdx.x % ntx;
-  const int rest = blockIdx.x / ntx;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);  // x-neighbour tiles share 128-byte lines: same L2
+  const int xt = lb % ntx;
+  const int rest = lb / ntx;
   const int mz = rest % d.H;
   const int c = rest / d.H;
   const int x = xt * C::TX + col;
@@ -92,8 +93,9 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __rest
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
   const int npair = d.nx / 2;
   const int ntx = (npair + C::TX - 1) / C::TX;
-  const int xt = blockIdx.x % ntx;
-  const int rest = blockIdx.x / ntx;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);  // x-neighbour tiles share 128-byte lines: same L2
+  const int xt = lb % ntx;
+  const int rest = lb / ntx;
   const int y = rest % d.ny;
   const int c = rest / d.ny;
   const int pp = xt * C::TX + col;
@@ -140,8 +142,9 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* _
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
   const int npair = d.nx / 2;
   const int ntx = (npair + C::TX - 1) / C::TX;
-  const int xt = blockIdx.x % ntx;
-  const int rest = blockIdx.x / ntx;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);  // x-neighbour tiles share 128-byte lines: same L2
+  const int xt = lb % ntx;
+  const int rest = lb / ntx;
   const int y = rest % d.ny;
   const int c = rest / d.ny;
   const int pp = xt * C::TX + col;

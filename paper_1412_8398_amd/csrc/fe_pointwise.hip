@@ -143,17 +143,32 @@ static int grid_for(long long n, int cap = 8192) {
 //   D_j(z) = P(z) + P(z-1) + Q(z-1) - Q(z).
 // WP uses the same walk with P = [s_xj(x) - s_xj(x-e_x)] + [s_yj(x) - s_yj(x-e_y)],
 // Q = s_zj(x): D_j(z) = P(z) + Q(z) - Q(z-1).
-constexpr int DX = 32, DY = 8;
+// Corner tile (x by y) of a workgroup, by the type held in LDS.  The -x halo
+// voxel of a tile costs a whole 128-byte line per row (and U a second one at
+// +x): wide tiles make that a small fraction.  Float: 128 x 8 (1024 threads,
+// 94 KiB of LDS); double: 64 x 8 (the LDS of a double 128 x 8 tile exceeds
+// 160 KiB).
+template <typename T>
+struct Tile;
+template <>
+struct Tile<float> {
+  static constexpr int DX = 128, DY = 8;
+};
+template <>
+struct Tile<double> {
+  static constexpr int DX = 64, DY = 8;
+};
 
 // Optional outputs/inputs (null to skip): Dtau receives the divergence of tau
 // (type TD), Dsig the divergence of sigma (type TS), and Dsig_base is added to
 // the divergence of sigma before it is squared for eta (the divergence of an
 // anchor strain when iterating on a correction).
 template <typename TS, typename TC, typename TD, int OP>
-__global__ __launch_bounds__(DX * DY) void k_div(const TS* __restrict__ eps, const uint8_t* __restrict__ phase,
+__global__ __launch_bounds__(Tile<TC>::DX * Tile<TC>::DY) void k_div(const TS* __restrict__ eps, const uint8_t* __restrict__ phase,
                                                  const PhaseCoef<TC>* __restrict__ coef, TD* __restrict__ Dtau,
                                                  TS* __restrict__ Dsig, const TS* __restrict__ Dsig_base,
                                                  double* __restrict__ partials, Dims d, int zchunk, Batch bt) {
+  constexpr int DX = Tile<TC>::DX, DY = Tile<TC>::DY;
   {
     const long long smp = bt.active ? bt.active[blockIdx.y] : 0;
     eps += smp * 6 * d.N;
@@ -292,13 +307,14 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 template <typename T, int OP, bool AS, bool RF>
-__global__ __launch_bounds__(DX * DY) void k_update_div(const T* __restrict__ U, const T* __restrict__ eps_in,
+__global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const T* __restrict__ U, const T* __restrict__ eps_in,
                                                         T* __restrict__ eps_out, const uint8_t* __restrict__ phase,
                                                         const PhaseCoef<T>* __restrict__ coef, int ncoef,
                                                         GreenConst<T> g, const T* __restrict__ rfield,
                                                         T* __restrict__ Dtau, const T* __restrict__ Dsig_base,
                                                         double* __restrict__ partials, Dims d, int zchunk, Batch bt,
                                                         const GreenConst<T>* __restrict__ gs) {
+  constexpr int DX = Tile<T>::DX, DY = Tile<T>::DY;
   const long long N = d.N;
   {
     const long long smp = bt.active ? bt.active[blockIdx.y] : 0;
@@ -497,15 +513,19 @@ __global__ __launch_bounds__(DX * DY) void k_update_div(const T* __restrict__ U,
   }
 }
 
-// Tiling of the divergence walk: DX x DY corner tiles, z cut into chunks so
-// that there are about 8192 workgroups (at most 16384 partial sums).
+// Tiling of the divergence walk: one corner tile and z chunk per workgroup,
+// z cut into chunks of at least 8 planes so that a launch has about 2M
+// threads (several generations of resident workgroups on 256 CUs).
 struct DivGrid {
   int blocks, zchunk;
 };
+template <typename TC>
 static DivGrid div_grid(const Dims& d) {
+  constexpr int DX = Tile<TC>::DX, DY = Tile<TC>::DY;
   const int ntx = (d.nx + DX - 1) / DX, nty = (d.ny + DY - 1) / DY;
   const int bxy = ntx * nty;
-  int nch = (8192 + bxy - 1) / bxy;  // several waves of resident workgroups
+  const int target = (1 << 21) / (DX * DY);
+  int nch = (target + bxy - 1) / bxy;
   if (nch > d.nz / 8) nch = d.nz / 8;  // chunks of at least 8 planes (one halo plane each)
   if (nch < 1) nch = 1;
   const int zchunk = (d.nz + nch - 1) / nch;
@@ -513,7 +533,10 @@ static DivGrid div_grid(const Dims& d) {
   return DivGrid{bxy * nch, zchunk};
 }
 
-int div_partial_count(Dims d) { return div_grid(d).blocks; }
+int div_partial_count(Dims d) {
+  const int a = div_grid<float>(d).blocks, b = div_grid<double>(d).blocks;
+  return a > b ? a : b;
+}
 
 // --------------------------------------------------------------------------
 // strain update from the displacement U (WP, ROT)
@@ -761,8 +784,9 @@ void Launch<T>::check_phase(const uint8_t* phase, long long N, int n_phases, int
 template <typename T>
 int Launch<T>::div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, const T* Dsig_base,
                    double* partials, Dims d, int op, hipStream_t s, Batch bt, int nsamp) {
-  const DivGrid gd = div_grid(d);
+  const DivGrid gd = div_grid<T>(d);
   const dim3 grid(gd.blocks, nsamp);
+  constexpr int DX = Tile<T>::DX, DY = Tile<T>::DY;
   if (op == OP_ROT)
     hipLaunchKernelGGL((k_div<T, T, T, OP_ROT>), grid, dim3(DX * DY), 0, s, eps, phase, coef, D, (T*)nullptr,
                        Dsig_base, partials, d, gd.zchunk, bt);
@@ -776,8 +800,8 @@ template <typename T>
 int Launch<T>::update_div(const T* U, const T* eps_in, T* eps_out, const uint8_t* phase, const PhaseCoef<T>* coef,
                           GreenConst<T> g, const T* rfield, T* D, const T* Dsig_base, double* partials, Dims d, int op,
                           int accelerated, hipStream_t s, Batch bt, const GreenConst<T>* gs, int nsamp) {
-  const DivGrid gd = div_grid(d);
-  const dim3 grid(gd.blocks, nsamp), block(DX * DY);
+  const DivGrid gd = div_grid<T>(d);
+  const dim3 grid(gd.blocks, nsamp), block(Tile<T>::DX * Tile<T>::DY);
   // phase constants staged in LDS: a sample's table (batched) or the plan's 256 entries
   const int ncoef = bt.active ? (bt.ncoef < 256 ? bt.ncoef : 256) : 256;
 #define FE_UD(OPV, ASV)                                                                                          \
@@ -813,8 +837,9 @@ int launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<doubl
 template <typename TS>
 int launch_div64(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* Dtau, TS* Dsig,
                  double* partials, Dims d, int op, hipStream_t s, Batch bt, int nsamp) {
-  const DivGrid gd = div_grid(d);
+  const DivGrid gd = div_grid<double>(d);
   const dim3 grid(gd.blocks, nsamp);
+  constexpr int DX = Tile<double>::DX, DY = Tile<double>::DY;
   if (op == OP_ROT)
     hipLaunchKernelGGL((k_div<TS, double, double, OP_ROT>), grid, dim3(DX * DY), 0, s, eps, phase, coef, Dtau, Dsig,
                        (const TS*)nullptr, partials, d, gd.zchunk, bt);
