@@ -229,7 +229,9 @@ def main():
         "frac": round(passes[dom]["gbs"] / PEAK_HBM_GBS, 4),
         "traffic": measured_traffic(dom, L),
     }
-    step_bytes = sum(pb.values())
+    # one iteration: the five transform passes and the fused update (the
+    # stand-alone divergence runs once per solve)
+    step_bytes = sum(v for k, v in pb.items() if k != "pointwise")
     iter_gbs = step_bytes * K / wall / 1e9
 
     tti = None
@@ -267,6 +269,7 @@ def main():
         "time_to_tol_1e-6": tti,
         "iteration_bytes_model": step_bytes,
         "iteration_gbs_model": round(iter_gbs, 1),
+        "iteration_hbm_frac_model": round(iter_gbs / PEAK_HBM_GBS, 4),
         "passes": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                    for k, v in passes.items()},
         "library_seconds": round(res.seconds, 4),

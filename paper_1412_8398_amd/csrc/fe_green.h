@@ -34,6 +34,10 @@ __device__ __forceinline__ void woodbury_solve(const cpx<T> (&k)[3], const cpx<T
   for (int a = 0; a < 3; ++a) x[a] = scale(sub(sub(b[a], mul(conj(k[a]), y1)), mul(k[a], y2)), iD);
 }
 
+// 1/x: the hardware reciprocal (1 ulp) in float, a division in double.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // k(q) from the per-axis tables.
 //   MS : k = i q                        (eqs. (7)-(8))
 //   WP : k = exp(i q) - 1               (eq. (21))
@@ -78,8 +82,9 @@ __device__ __forceinline__ void green_disp(cpx<T> (&b)[3], const WaveTables<T>& 
     const T tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
     if (tt > T(0)) {
       const cpx<T> tb = add(add(scale(b[0], t[0]), scale(b[1], t[1])), scale(b[2], t[2]));
-      const T f = -g.inv_n / (T(4) * g.mu0 * tt);
-      const T h = g.cr / tt;
+      const T itt = recip(tt);
+      const T f = -g.inv_n / (T(4) * g.mu0) * itt;
+      const T h = g.cr * itt;
 #pragma unroll
       for (int a = 0; a < 3; ++a) b[a] = scale(sub(b[a], scale(tb, h * t[a])), f);
     } else {

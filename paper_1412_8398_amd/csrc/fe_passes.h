@@ -202,7 +202,9 @@ __global__ __launch_bounds__((LineCfg<T, N, 3>::NT)) void k_xgreen3(cpx<T>* __re
     S += smp * 3 * d.H * d.ny * d.nx;
     if (gs) g = gs[smp];
   }
-  __shared__ cpx<T> lds[C::LPB * C::LINE];
+  // the three components exchange through LDS together (51 KiB at 512):
+  // a third of the barriers of taking turns
+  __shared__ cpx<T> lds[3 * C::LPB * C::LINE];
   const int t = threadIdx.x % C::P, l = threadIdx.x / C::P;
   const int nlines = d.H * d.ny;
   const int line = blockIdx.x * C::LPB + l;
@@ -214,8 +216,8 @@ __global__ __launch_bounds__((LineCfg<T, N, 3>::NT)) void k_xgreen3(cpx<T>* __re
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int m = 0; m < C::E; ++m) v[c][m] = ok ? base[c * cs + m * C::P] : mk(T(0), T(0));
-  const auto at = [l](int, int pos) { return l * C::LINE + pad16(pos); };
-  fft_regs<T, N, C::E, 3, false, true>(v, t, lds, at, tw);
+  const auto at = [l](int c, int pos) { return (c * C::LPB + l) * C::LINE + pad16(pos); };
+  fft_regs<T, N, C::E, 3, false>(v, t, lds, at, tw);
   const int mz = (ok ? line : 0) / d.ny, my = (ok ? line : 0) % d.ny;
 #pragma unroll
   for (int m = 0; m < C::E; ++m) {
@@ -224,7 +226,7 @@ __global__ __launch_bounds__((LineCfg<T, N, 3>::NT)) void k_xgreen3(cpx<T>* __re
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[c][m] = b[c];
   }
-  fft_regs<T, N, C::E, 3, true, true>(v, t, lds, at, tw);
+  fft_regs<T, N, C::E, 3, true>(v, t, lds, at, tw);
   if (ok) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
