@@ -52,9 +52,12 @@ typedef enum {
 
 /* Discrete Green operator (§3, §4 of the paper). */
 typedef enum {
-  FE_GREEN_MS = 0,  /* continuous operator, k = i q, eqs. (8), (14)       */
-  FE_GREEN_WP = 1,  /* Willot-Pellegrini, k = exp(i q) - 1, eq. (21)       */
-  FE_GREEN_ROT = 2  /* rotated grid, k of eq. (36), special modes eq. (41)  */
+  FE_GREEN_MS = 0,      /* continuous operator, k = i q, eqs. (8), (14)       */
+  FE_GREEN_WP = 1,      /* Willot-Pellegrini, k = exp(i q) - 1, eq. (21)       */
+  FE_GREEN_ROT = 2,     /* rotated grid, k of eq. (36), special modes eq. (41)  */
+  FE_GREEN_CENTERED = 3 /* centered differences, k = i sin q (§4.2); zero where
+                           every q_i is 0 or pi, eq. (29).  Six-component form
+                           like FE_GREEN_MS (no float64 re-anchoring).       */
 } fe_discretization;
 
 typedef enum { FE_DIRECT = 0, FE_ACCELERATED = 1 } fe_scheme; /* eqs. (9), (16) */

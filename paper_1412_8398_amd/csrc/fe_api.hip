@@ -68,6 +68,11 @@ static std::vector<double> wave_table(int n, int op) {
       cos_sin(mp, 2L * n, &ch, &sh);
       w[2 * m] = -2.0 * sh * sh;
       w[2 * m + 1] = 2.0 * sh * ch;
+    } else if (op == OP_C) {  // sin q, exactly 0 at q = 0 and q = pi
+      double c, s;
+      cos_sin(mp, n, &c, &s);
+      w[2 * m] = s;
+      w[2 * m + 1] = 0.0;
     } else {  // MS
       w[2 * m] = 2.0 * M_PI * (double)mp / (double)n;
       w[2 * m + 1] = (n % 2 == 0 && 2 * m == n) ? 1.0 : 0.0;
@@ -213,7 +218,8 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
                   sizeof(fe_plan_options));
     o = *opt;
   }
-  if (disc < FE_GREEN_MS || disc > FE_GREEN_ROT) return fail(FE_ERR_INVALID_ARG, "unknown discretization %d", (int)disc);
+  if (disc < FE_GREEN_MS || disc > FE_GREEN_CENTERED)
+    return fail(FE_ERR_INVALID_ARG, "unknown discretization %d", (int)disc);
   if (scheme != FE_DIRECT && scheme != FE_ACCELERATED) return fail(FE_ERR_INVALID_ARG, "unknown scheme %d", (int)scheme);
   if (o.precision != FE_FP32 && o.precision != FE_FP64)
     return fail(FE_ERR_INVALID_ARG, "unknown precision %d", (int)o.precision);
@@ -240,8 +246,8 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
   p->scheme = scheme;
   p->opt = o;
   p->stream = (hipStream_t)o.hip_stream;
-  p->op = disc == FE_GREEN_MS ? OP_MS : (disc == FE_GREEN_WP ? OP_WP : OP_ROT);
-  p->displacement = p->op != OP_MS;
+  p->op = disc == FE_GREEN_MS ? OP_MS : disc == FE_GREEN_WP ? OP_WP : disc == FE_GREEN_ROT ? OP_ROT : OP_C;
+  p->displacement = p->op == OP_WP || p->op == OP_ROT;
   p->d.nx = g.nx;
   p->d.ny = g.ny;
   p->d.nz = g.nz;
@@ -1144,7 +1150,7 @@ extern "C" fe_status fe_solve_batched(fe_discretization disc, fe_scheme scheme, 
                                       double* seconds) {
   if (!desc || !results) return fail(FE_ERR_INVALID_ARG, "desc or results is NULL");
   if (disc != FE_GREEN_WP && disc != FE_GREEN_ROT)
-    return fail(disc == FE_GREEN_MS ? FE_ERR_UNSUPPORTED : FE_ERR_INVALID_ARG,
+    return fail(disc == FE_GREEN_MS || disc == FE_GREEN_CENTERED ? FE_ERR_UNSUPPORTED : FE_ERR_INVALID_ARG,
                 "batched solves support the WP and ROT operators");
   if (scheme != FE_DIRECT && scheme != FE_ACCELERATED) return fail(FE_ERR_INVALID_ARG, "unknown scheme");
   fe_plan_options o;

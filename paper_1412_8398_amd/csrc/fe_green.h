@@ -40,6 +40,7 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // k(q) from the per-axis tables.
 //   MS : k = i q                        (eqs. (7)-(8))
+//   C  : k = i sin q                    (centered differences, §4.2)
 //   WP : k = exp(i q) - 1               (eq. (21))
 //   ROT: k = 2 i exp(i (q1+q2+q3)/2) t, t_a = sin(q_a/2) prod_{b!=a} cos(q_b/2)  (eq. (36))
 template <typename T, int OP>
@@ -51,7 +52,7 @@ __device__ __forceinline__ void wave_k(const WaveTables<T>& wt, int mx, int my, 
     k[0] = mk(ax, bx);
     k[1] = mk(ay, by);
     k[2] = mk(az, bz);
-  } else if (OP == OP_MS) {
+  } else if (OP == OP_MS || OP == OP_C) {  // i q or i sin q
     k[0] = mk(T(0), ax);
     k[1] = mk(T(0), ay);
     k[2] = mk(T(0), az);
@@ -108,7 +109,8 @@ __device__ __forceinline__ void green_disp(cpx<T> (&b)[3], const WaveTables<T>& 
 // Six-component form (any operator): tau(q) -> eps(q)/N.
 //   q = 0: eps_bar (eq. (6));  MS with some q_i = pi: -(C0)^-1 tau (eq. (14));
 //   ordinary: b_j = conj(k_i) tau_ij, u = -A^-1 b, eps = sym(k (x) u) (eq. (19));
-//   ROT with two q_i = pi: |k| = 0, eps = 0 (eq. (41)).
+//   ROT with two q_i = pi: |k| = 0, eps = 0 (eq. (41));
+//   C with every q_i in {0, pi}: |k| = 0, eps = 0 (eq. (29)).
 template <typename T, int OP>
 __device__ __forceinline__ void green_six(cpx<T> (&tv)[6], const WaveTables<T>& wt, int mx, int my, int mz,
                                           const GreenConst<T>& g) {

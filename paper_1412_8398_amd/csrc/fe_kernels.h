@@ -8,7 +8,7 @@
 
 namespace fe {
 
-enum Op { OP_MS = 0, OP_WP = 1, OP_ROT = 2 };
+enum Op { OP_MS = 0, OP_WP = 1, OP_ROT = 2, OP_C = 3 };
 
 struct Dims {
   int nx, ny, nz, H;  // H = nz/2 + 1 (half spectrum along z)

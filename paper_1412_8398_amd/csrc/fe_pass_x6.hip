@@ -14,6 +14,7 @@ void Launch<T>::xgreen6(cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> wt, 
     switch (op) {
       case OP_MS: hipLaunchKernelGGL((k_xgreen6<T, N, OP_MS>), grid, block, 0, s, S, d, twx, wt, g); break;
       case OP_WP: hipLaunchKernelGGL((k_xgreen6<T, N, OP_WP>), grid, block, 0, s, S, d, twx, wt, g); break;
+      case OP_C: hipLaunchKernelGGL((k_xgreen6<T, N, OP_C>), grid, block, 0, s, S, d, twx, wt, g); break;
       default: hipLaunchKernelGGL((k_xgreen6<T, N, OP_ROT>), grid, block, 0, s, S, d, twx, wt, g); break;
     }
   });
@@ -31,6 +32,7 @@ int Launch<T>::xeta6(const cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> w
     switch (op) {
       case OP_MS: hipLaunchKernelGGL((k_xeta6<T, N, OP_MS>), grid, block, 0, s, S, d, twx, wt, partials); break;
       case OP_WP: hipLaunchKernelGGL((k_xeta6<T, N, OP_WP>), grid, block, 0, s, S, d, twx, wt, partials); break;
+      case OP_C: hipLaunchKernelGGL((k_xeta6<T, N, OP_C>), grid, block, 0, s, S, d, twx, wt, partials); break;
       default: hipLaunchKernelGGL((k_xeta6<T, N, OP_ROT>), grid, block, 0, s, S, d, twx, wt, partials); break;
     }
   });

@@ -146,8 +146,8 @@ static int grid_for(long long n, int cap = 8192) {
 // Corner tile (x by y) of a workgroup, by the type held in LDS.  The -x halo
 // voxel of a tile costs a whole 128-byte line per row (and U a second one at
 // +x): wide tiles make that a small fraction.  Float: 128 x 8 (1024 threads,
-// 94 KiB of LDS); double: 64 x 8 (the LDS of a double 128 x 8 tile exceeds
-// 160 KiB).
+// 94 KiB of LDS); double: 32 x 8 (a double 128 x 8 tile does not fit in
+// 160 KiB, and 64 x 8 ran the float64 verification stencil slower).
 template <typename T>
 struct Tile;
 template <>
@@ -156,7 +156,7 @@ struct Tile<float> {
 };
 template <>
 struct Tile<double> {
-  static constexpr int DX = 64, DY = 8;
+  static constexpr int DX = 32, DY = 8;
 };
 
 // Optional outputs/inputs (null to skip): Dtau receives the divergence of tau

@@ -73,7 +73,7 @@ def test_config1_direct_rotated_fp64_full_solve():
 
 
 @pytest.mark.parametrize("scheme", ["DS", "AS"])
-@pytest.mark.parametrize("op", ["MS", "W", "R"])
+@pytest.mark.parametrize("op", ["MS", "W", "R", "C"])
 def test_equal_iteration_parity_fp64(op, scheme):
     shape = (24, 16, 48)  # (nz, ny, nx): lengths 3*2^3, 2^4, 3*2^4
     phase, E, nu = _three_phase(shape)
@@ -86,7 +86,7 @@ def test_equal_iteration_parity_fp64(op, scheme):
 
 
 @pytest.mark.parametrize("scheme", ["DS", "AS"])
-@pytest.mark.parametrize("op", ["MS", "W", "R"])
+@pytest.mark.parametrize("op", ["MS", "W", "R", "C"])
 def test_equal_iteration_parity_fp32(op, scheme):
     shape = (24, 16, 48)
     phase, E, nu = _three_phase(shape)
@@ -101,10 +101,10 @@ def test_equal_iteration_parity_fp32(op, scheme):
     assert abs(res.eta_verify_fp64 - want) <= 1e-9 * want
 
 
-@pytest.mark.parametrize("shape", [(384, 12, 48), (12, 768, 24)])
+@pytest.mark.parametrize("shape", [(384, 12, 48), (12, 768, 24), (256, 8, 12), (128, 6, 16)])
 def test_ragged_tiles_parity_fp64(shape):
     """Grids whose FFT passes end in partial tiles (z-pass column tiles, y-pass
-    column tiles, x-pass line blocks)."""
+    column tiles, x-pass line blocks), and long z columns (nz = 128 to 384)."""
     phase, E, nu = _three_phase(shape, seed=11)
     k = 3
     ref = O.solve(phase, E, nu, MACRO, op="R", scheme="AS", tol=1e-300, max_iter=k)
@@ -112,12 +112,28 @@ def test_ragged_tiles_parity_fp64(shape):
     assert _rel(eps, O.tensor_to_voigt(ref.eps)) < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(192, 8, 12), (512, 4, 8), (768, 4, 6), (96, 8, 12)])
+def test_long_z_parity(shape):
+    """Long z columns (nz = 96 to 768: every tile width of the strided
+    passes), element by element against the oracle after 3 iterations: float64
+    to 1e-12 (any indexing slip shows at 1e-3 or more), float32 to 5e-5 (the
+    rounding of float32 transforms along a 768-long axis in a contrast-50
+    cell; the (24, 16, 48) cases stay below 2e-5)."""
+    phase, E, nu = _three_phase(shape, seed=12)
+    k = 3
+    ref = O.tensor_to_voigt(O.solve(phase, E, nu, MACRO, op="R", scheme="AS", tol=1e-300, max_iter=k).eps)
+    _, eps64 = _run(phase, E, nu, MACRO, "R", "AS", "fp64", k=k)
+    assert _rel(eps64, ref) < 1e-12
+    _, eps32 = _run(phase, E, nu, MACRO, "R", "AS", "fp32", k=k)
+    assert _rel(eps32, ref) < 5e-5
+
+
 def test_warm_start_parity_fp64(rng):
     shape = (16, 24, 12)
     phase, E, nu = _three_phase(shape, seed=3)
     start = O.tensor_to_voigt(O.voigt_to_tensor(rng.standard_normal((6,) + shape)))
     k = 3
-    for op in ("R", "MS"):
+    for op in ("R", "MS", "C"):
         ref = O.solve(phase, E, nu, MACRO, op=op, scheme="AS", tol=1e-300, max_iter=k,
                       eps_init=O.voigt_to_tensor(start))
         res, eps = _run(phase, E, nu, MACRO, op, "AS", "fp64", k=k, strain_init=start)
@@ -125,7 +141,7 @@ def test_warm_start_parity_fp64(rng):
         assert np.allclose(res.eta_history, ref.eta_history, rtol=1e-10, atol=1e-14)
 
 
-@pytest.mark.parametrize("op", ["MS", "W", "R"])
+@pytest.mark.parametrize("op", ["MS", "W", "R", "C"])
 def test_homogeneous_medium_converges_in_one_step(op, rng):
     shape = (8, 12, 16)
     phase = (rng.random(shape) < 0.5).astype(np.uint8)
@@ -178,6 +194,20 @@ def test_direct_scheme_below_half_reports_divergence():
     res, _ = _run(phase, [1.0, 50.0], [0.3, 0.3], [1, 0, 0, 0, 0, 0], "R", "DS", "fp64", tol=1e-12,
                   max_iter=3000, ds_beta=0.45, diverge_window=30)
     assert res.status == fe.FE_DIVERGED
+
+
+def test_centered_operator_converges_to_the_oracle_solution():
+    """G^C (§4.2): a full AS solve to 1e-10 in float64 reaches the oracle's
+    iteration count, mean stress and field."""
+    phase = sphere_inclusion((16, 16, 16), (8, 8, 8), 5.0)
+    E, nu = [1.0, 10.0], [0.3, 0.3]
+    ref = O.solve(phase, E, nu, MACRO, op="C", scheme="AS", tol=1e-10, max_iter=2000)
+    res, eps = _run(phase, E, nu, MACRO, "C", "AS", "fp64", tol=1e-10, max_iter=2000)
+    assert res.status == fe.FE_OK
+    assert res.iterations == ref.iterations
+    assert _rel(eps, O.tensor_to_voigt(ref.eps)) < 1e-10
+    want = O.tensor_to_voigt(ref.mean_stress)
+    assert np.allclose(res.mean_stress, want, rtol=1e-10, atol=1e-12)
 
 
 def test_runs_are_bitwise_deterministic():
