@@ -93,6 +93,8 @@ void pool_backward_add(const uint16_t* gpool, const uint16_t* gcat, int ca, int 
 int bias_grad(const uint16_t* dy, const uint16_t* ymask, int c, float* partials, float* db, Grid3 g, hipStream_t s);
 
 // head: p = d1 hw + hb (16 -> 6); per-sample sums of p (and of the target)
+// Blocks per sample of head_stats / head_backward (their partial sums).
+int head_blocks(Grid3 g);
 int head_stats(const uint16_t* d1, const float* hw, const float* hb, const void* target, int target_bf16,
                double* partials, double* sums, Grid3 g, hipStream_t s);
 // prediction eps = p - mean(p) + eps_bar, written as float [sample][6][N]

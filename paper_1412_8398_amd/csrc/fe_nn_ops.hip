@@ -285,7 +285,16 @@ int bias_grad(const uint16_t* dy, const uint16_t* ymask, int c, float* partials,
 // ---------------------------------------------------------------------------
 // head (16 -> 6, linear), mean correction, loss
 // ---------------------------------------------------------------------------
-constexpr int kHeadBlocks = 64;  // blocks per sample
+// Blocks per sample of the head kernels: about 2048 in all (a single 512^3
+// prediction needs the whole chip), 64 to 1024 per sample, never more than
+// the sample's voxels fill.
+int head_blocks(Grid3 g) {
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  int b = 2048 / (g.nb > 0 ? g.nb : 1);
+  b = b < 64 ? 64 : (b > 1024 ? 1024 : b);
+  const long long fill = (N + 255) / 256;
+  return (int)(b > fill ? fill : b);
+}
 
 __device__ __forceinline__ void head_eval(const u32x4* __restrict__ d1, long long v, const float* __restrict__ hw,
                                           const float* __restrict__ hb, float (&x)[16], float (&p)[6]) {
@@ -342,10 +351,11 @@ __global__ void k_head_sums(const double* __restrict__ partials, int nblk, doubl
 
 int head_stats(const uint16_t* d1, const float* hw, const float* hb, const void* target, int target_bf16,
                double* partials, double* sums, Grid3 g, hipStream_t s) {
-  hipLaunchKernelGGL(k_head_stats, dim3(kHeadBlocks, g.nb), dim3(256), 0, s, reinterpret_cast<const u32x4*>(d1), hw, hb,
+  const int hb_n = head_blocks(g);
+  hipLaunchKernelGGL(k_head_stats, dim3(hb_n, g.nb), dim3(256), 0, s, reinterpret_cast<const u32x4*>(d1), hw, hb,
                      target, target_bf16, partials, g);
-  hipLaunchKernelGGL(k_head_sums, dim3(g.nb), dim3(64), 0, s, partials, kHeadBlocks, sums);
-  return kHeadBlocks;
+  hipLaunchKernelGGL(k_head_sums, dim3(g.nb), dim3(64), 0, s, partials, hb_n, sums);
+  return hb_n;
 }
 
 __global__ void k_head_predict(const u32x4* __restrict__ d1, const float* __restrict__ hw, const float* __restrict__ hb,
@@ -472,12 +482,13 @@ __global__ void k_head_backward_reduce(const double* __restrict__ partials, int 
 int head_backward(const uint16_t* d1, const float* hw, const float* hb, const double* sums, const FeatTab* tabs,
                   const void* target, int target_bf16, uint16_t* gd1, double* partials, double* out_loss, float* ghw,
                   float* ghb, Grid3 g, hipStream_t s) {
-  hipLaunchKernelGGL(k_head_backward, dim3(kHeadBlocks, g.nb), dim3(256), 0, s, reinterpret_cast<const u32x4*>(d1), hw,
+  const int hb_n = head_blocks(g);
+  hipLaunchKernelGGL(k_head_backward, dim3(hb_n, g.nb), dim3(256), 0, s, reinterpret_cast<const u32x4*>(d1), hw,
                      hb, sums, tabs, target, target_bf16, reinterpret_cast<u32x4*>(gd1), partials, g);
   const double scale = 1.0 / ((double)g.nb * 6.0 * (double)g.nx * g.ny * g.nz);
-  hipLaunchKernelGGL(k_head_backward_reduce, dim3(1), dim3(128), 0, s, partials, kHeadBlocks * g.nb, out_loss, ghw, ghb,
+  hipLaunchKernelGGL(k_head_backward_reduce, dim3(1), dim3(128), 0, s, partials, hb_n * g.nb, out_loss, ghw, ghb,
                      scale);
-  return kHeadBlocks;
+  return hb_n;
 }
 
 // ---------------------------------------------------------------------------

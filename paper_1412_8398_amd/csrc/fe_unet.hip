@@ -287,7 +287,7 @@ static fe_status ensure_workspace(fe_unet* n, const Grid3& g, bool grads) {
   n->ba = take(V4 * 128);
   n->bt = take(V4 * 128);
   HIP_TRY(n->tabs.ensure((size_t)g.nb));
-  HIP_TRY(n->hpart.ensure((size_t)g.nb * 64 * 103 + 64));
+  HIP_TRY(n->hpart.ensure((size_t)g.nb * head_blocks(g) * 103 + 64));
   HIP_TRY(n->sums.ensure((size_t)g.nb * 12));
   HIP_TRY(n->loss.ensure(1));
   if (grads) {
