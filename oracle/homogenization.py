@@ -22,7 +22,7 @@ eye against the paper:
 * the direct and accelerated schemes, eqs. (9) and (16), are run step by step
   so that iterates can be compared at equal iteration index.
 
-Readings of the paper taken here (each is also listed in the design doc):
+Readings of the paper taken here:
   R1  eq. (24) is read with gradient k and divergence conj(k): the operator
       is sym[k_i (A^-1)_jk conj(k_l)] with A = lam0 conj(k) k^T
       + mu0 k conj(k)^T + mu0 |k|^2 I.  This is the operator that eq. (19)
