@@ -248,11 +248,7 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
   p->stream = (hipStream_t)o.hip_stream;
   p->op = disc == FE_GREEN_MS ? OP_MS : disc == FE_GREEN_WP ? OP_WP : disc == FE_GREEN_ROT ? OP_ROT : OP_C;
   p->displacement = p->op == OP_WP || p->op == OP_ROT;
-  p->d.nx = g.nx;
-  p->d.ny = g.ny;
-  p->d.nz = g.nz;
-  p->d.H = g.nz / 2 + 1;
-  p->d.N = (long long)g.nx * g.ny * g.nz;
+  p->d = make_dims(g.nx, g.ny, g.nz);
   long long db = (p->d.N + kThreads - 1) / kThreads;
   p->div_blocks = (int)(db > kMaxReduceBlocks ? kMaxReduceBlocks : db);
 
@@ -266,7 +262,7 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
   const size_t es = elem_size(p);
   const int ncomp = p->displacement ? 3 : 6;
   const long long N = p->d.N;
-  const size_t spec = (size_t)p->d.H * g.ny * g.nx;
+  const size_t spec = (size_t)spec_size(p->d);
   fe_status st;
   hipError_t e;
   if ((e = dmalloc(p, &p->R, (size_t)ncomp * N * es)) != hipSuccess)
@@ -274,7 +270,7 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
   if ((e = dmalloc(p, &p->S, (size_t)ncomp * spec * 2 * es)) != hipSuccess)
     return cleanup_fail(fail(e == hipErrorOutOfMemory ? FE_ERR_OOM : FE_ERR_DEVICE, "workspace S: %s", hipGetErrorString(e)));
   // partial sums: div/tau blocks x 7, and one per x-line block of the spectral eta
-  const size_t lines = (size_t)p->d.H * g.ny;
+  const size_t lines = (size_t)p->d.Hp * g.ny;
   p->partial_count = (size_t)kMaxReduceBlocks * 7;
   if ((e = dmalloc(p, (void**)&p->partials, p->partial_count * sizeof(double))) != hipSuccess ||
       (e = dmalloc(p, (void**)&p->partials2, (lines + 1) * sizeof(double))) != hipSuccess ||
@@ -432,7 +428,7 @@ static fe_status verify_fp64(fe_plan* p, const TS* eps, const uint8_t* phase, do
   }
   double *e64 = nullptr, *r64 = nullptr;
   cpx<double>* s64 = nullptr;
-  const size_t spec = (size_t)d.H * d.ny * d.nx;
+  const size_t spec = (size_t)spec_size(d);
   if (hipMalloc(&e64, 6 * (size_t)d.N * 8) != hipSuccess || hipMalloc(&r64, 6 * (size_t)d.N * 8) != hipSuccess ||
       hipMalloc(&s64, 6 * spec * sizeof(cpx<double>)) != hipSuccess) {
     if (e64) (void)hipFree(e64);
@@ -563,7 +559,7 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
 
   // float64 re-anchor at the strain eps (+ it if anchored)
   auto reanchor = [&]() -> fe_status {
-    const size_t spec = (size_t)d.H * d.ny * d.nx;
+    const size_t spec = (size_t)spec_size(d);
     {
       fe_status ss = sync_iterate();
       if (ss != FE_OK) return ss;
@@ -901,7 +897,7 @@ template <typename T>
 fe_status alloc_class(BatchClass<T>& c, int op) {
   const size_t n = c.ids.size();
   const long long N = c.d.N;
-  const size_t spec = (size_t)c.d.H * c.d.ny * c.d.nx;
+  const size_t spec = (size_t)spec_size(c.d);
   HIP_TRY(hipMalloc((void**)&c.eps, n * 6 * N * sizeof(T)));
   HIP_TRY(hipMalloc((void**)&c.eps2, n * 6 * N * sizeof(T)));
   HIP_TRY(hipMalloc((void**)&c.R, n * 3 * N * sizeof(T)));
@@ -943,7 +939,7 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
       if (cls[c].d.nx == g.nx && cls[c].d.ny == g.ny && cls[c].d.nz == g.nz) break;
     if (c == cls.size()) {
       BatchClass<T> bc;
-      bc.d = Dims{g.nx, g.ny, g.nz, g.nz / 2 + 1, (long long)g.nx * g.ny * g.nz};
+      bc.d = make_dims(g.nx, g.ny, g.nz);
       cls.push_back(bc);
     }
     cls[c].ids.push_back(i);

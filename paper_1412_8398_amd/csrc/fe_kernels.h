@@ -13,7 +13,46 @@ enum Op { OP_MS = 0, OP_WP = 1, OP_ROT = 2, OP_C = 3 };
 struct Dims {
   int nx, ny, nz, H;  // H = nz/2 + 1 (half spectrum along z)
   long long N;        // nx*ny*nz
+  int zs;             // the transform work buffers group z in blocks of 2^zs planes
+  int Hp;             // half-spectrum planes stored: H rounded up to 2^zs
 };
+
+// Grid dimensions with the z blocking of the transform work buffers: blocks
+// of 8 planes where nz allows (else the largest power of two dividing nz).
+inline Dims make_dims(int nx, int ny, int nz) {
+  Dims d;
+  d.nx = nx;
+  d.ny = ny;
+  d.nz = nz;
+  d.H = nz / 2 + 1;
+  d.N = (long long)nx * ny * nz;
+  d.zs = 3;
+  while (d.zs > 0 && nz % (1 << d.zs) != 0) --d.zs;
+  d.Hp = ((d.H + (1 << d.zs) - 1) >> d.zs) << d.zs;
+  return d;
+}
+
+// Layout of the transform work buffers (divergence / displacement planes,
+// six-component polarization planes, half spectra): row (z, y) of a component
+// sits at ((z >> zs) ny + y) 2^zs + (z mod 2^zs), x fastest.  A column along z
+// then crosses nz / 2^zs page-sized strides instead of nz (address
+// translation: one 2 MiB page per plane at 1024^2 planes).  The strain, phase
+// and stress fields keep the plain [z][y][x] layout.
+__host__ __device__ __forceinline__ long long zrow(const Dims& d, int z, int y) {
+  return (((long long)(z >> d.zs) * d.ny + y) << d.zs) + (z & ((1 << d.zs) - 1));
+}
+// element of the blocked layout holding plain voxel (z, y, x)
+__host__ __device__ __forceinline__ long long zidx(const Dims& d, int z, int y, int x) {
+  return zrow(d, z, y) * d.nx + x;
+}
+// plain voxel index v = (z ny + y) nx + x -> blocked element
+__host__ __device__ __forceinline__ long long zblk(const Dims& d, long long v) {
+  if (d.zs == 0) return v;
+  const long long zy = v / d.nx;
+  return zidx(d, (int)(zy / d.ny), (int)(zy % d.ny), (int)(v - zy * d.nx));
+}
+// half-spectrum values per component (padded planes included)
+__host__ __device__ __forceinline__ long long spec_size(const Dims& d) { return (long long)d.Hp * d.ny * d.nx; }
 
 // Per-phase constants derived on the host in float64 from (E, nu) and C0.
 template <typename T>
@@ -36,7 +75,7 @@ struct GreenConst {
 
 // Batched launches: blockIdx.y selects a slot of the active-sample list; every
 // per-sample buffer of a size class is packed with a fixed stride (strain 6N,
-// phase N, real work planes ncomp*N, half spectra ncomp*H*ny*nx, partial sums
+// phase N, real work planes ncomp*N, half spectra ncomp*Hp*ny*nx, partial sums
 // gridDim.x*7, phase constants ncoef).
 struct Batch {
   const int* active;  // null: a single sample (sample 0)
@@ -65,14 +104,11 @@ struct Launch {
   // sums (7 doubles each) written.
   static int div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, const T* Dsig_base,
                  double* partials, Dims d, int op, hipStream_t s, Batch bt = Batch{nullptr, 0}, int nsamp = 1);
-  // rfield (nullable, 6 planes) replaces the constant applied strain; gs
-  // (nullable) holds per-sample constants that replace g.
-  static void grad_update(const T* U, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef,
-                          GreenConst<T> g, const T* rfield, Dims d, int op, int accelerated, hipStream_t s,
-                          Batch bt = Batch{nullptr, 0}, const GreenConst<T>* gs = nullptr, int nsamp = 1);
-  // grad_update then div in one walk: eps_out = update(U, eps_in) and D = div tau(eps_out)
-  // with eta's partial sums; eps_in and eps_out must not overlap.  Returns the
-  // number of partial sums (same tiling as div).
+  // Strain update then div in one walk: eps_out = update(U, eps_in) and D =
+  // div tau(eps_out) with eta's partial sums; eps_in and eps_out must not
+  // overlap.  rfield (nullable, 6 planes) replaces the constant applied
+  // strain; gs (nullable) holds per-sample constants that replace g.  Returns
+  // the number of partial sums (same tiling as div).
   static int update_div(const T* U, const T* eps_in, T* eps_out, const uint8_t* phase, const PhaseCoef<T>* coef,
                         GreenConst<T> g, const T* rfield, T* D, const T* Dsig_base, double* partials, Dims d,
                         int op, int accelerated, hipStream_t s, Batch bt = Batch{nullptr, 0},

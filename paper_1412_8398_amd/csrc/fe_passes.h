@@ -52,7 +52,7 @@ template <typename T, int N, bool INV>
 __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_ypass(cpx<T>* __restrict__ S, Dims d,
                                                                 const cpx<T>* __restrict__ tw, Batch bt) {
   using C = StridedCfg<T, N>;
-  if (bt.active) S += (long long)bt.active[blockIdx.y] * (gridDim.x / (((d.nx + C::TX - 1) / C::TX) * d.H)) * d.H * d.ny * d.nx;
+  if (bt.active) S += (long long)bt.active[blockIdx.y] * (gridDim.x / (((d.nx + C::TX - 1) / C::TX) * d.H)) * spec_size(d);
   __shared__ cpx<T> lds[N * C::TX];
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
   const int ntx = (d.nx + C::TX - 1) / C::TX;
@@ -63,14 +63,15 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_ypass(cpx<T>* __rest
   const int c = rest / d.H;
   const int x = xt * C::TX + col;
   const bool ok = x < d.nx;
-  cpx<T>* base = S + ((long long)c * d.H + mz) * (long long)N * d.nx + (ok ? x : 0);
+  cpx<T>* base = S + (long long)c * spec_size(d) + zidx(d, mz, 0, ok ? x : 0);
+  const long long ys = (long long)d.nx << d.zs;  // consecutive y rows of one plane
   cpx<T> v[1][C::E];
 #pragma unroll
-  for (int m = 0; m < C::E; ++m) v[0][m] = ok ? base[(long long)(t + m * C::P) * d.nx] : mk(T(0), T(0));
+  for (int m = 0; m < C::E; ++m) v[0][m] = ok ? base[(long long)(t + m * C::P) * ys] : mk(T(0), T(0));
   fft_regs<T, N, C::E, 1, INV>(v, t, lds, [col](int, int pos) { return pos * C::TX + col; }, tw);
   if (ok) {
 #pragma unroll
-    for (int m = 0; m < C::E; ++m) base[(long long)(t + m * C::P) * d.nx] = v[0][m];
+    for (int m = 0; m < C::E; ++m) base[(long long)(t + m * C::P) * ys] = v[0][m];
   }
 }
 
@@ -87,7 +88,7 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __rest
     const long long nc = gridDim.x / (((d.nx / 2 + C::TX - 1) / C::TX) * d.ny);
     const long long smp = bt.active[blockIdx.y];
     R += smp * nc * d.N;
-    S += smp * nc * d.H * d.ny * d.nx;
+    S += smp * nc * spec_size(d);
   }
   __shared__ cpx<T> lds[N * C::TX];
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
@@ -100,17 +101,16 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __rest
   const int c = rest / d.ny;
   const int pp = xt * C::TX + col;
   const bool ok = pp < npair;
-  const long long plane = (long long)d.ny * d.nx;
-  const T* src = R + (long long)c * d.N + (long long)y * d.nx + 2 * (ok ? pp : 0);
+  const T* src = R + (long long)c * d.N + 2 * (ok ? pp : 0);
   cpx<T> v[1][C::E];
 #pragma unroll
   for (int m = 0; m < C::E; ++m)
-    v[0][m] = ok ? *reinterpret_cast<const cpx<T>*>(src + (long long)(t + m * C::P) * plane) : mk(T(0), T(0));
+    v[0][m] = ok ? *reinterpret_cast<const cpx<T>*>(src + zrow(d, t + m * C::P, y) * d.nx) : mk(T(0), T(0));
   fft_regs<T, N, C::E, 1, false>(v, t, lds, [col](int, int pos) { return pos * C::TX + col; }, tw);
 #pragma unroll
   for (int m = 0; m < C::E; ++m) lds[(t + m * C::P) * C::TX + col] = v[0][m];
   __syncthreads();
-  cpx2<T>* dst = reinterpret_cast<cpx2<T>*>(S + (long long)c * d.H * plane + (long long)y * d.nx + 2 * (ok ? pp : 0));
+  cpx<T>* dst = S + (long long)c * spec_size(d) + 2 * (ok ? pp : 0);
   constexpr int H = N / 2 + 1, NS = (H + C::P - 1) / C::P;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
@@ -122,7 +122,7 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __rest
     cpx2<T> o;
     o.a = scale(add(Z, Zm), T(0.5));
     o.b = mk(T(0.5) * Dd.im, T(-0.5) * Dd.re);
-    if (ok) *reinterpret_cast<cpx2<T>*>(reinterpret_cast<cpx<T>*>(dst) + (long long)mz * plane) = o;
+    if (ok) *reinterpret_cast<cpx2<T>*>(dst + zrow(d, mz, y) * d.nx) = o;
   }
 }
 
@@ -136,7 +136,7 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* _
     const long long nc = gridDim.x / (((d.nx / 2 + C::TX - 1) / C::TX) * d.ny);
     const long long smp = bt.active[blockIdx.y];
     R += smp * nc * d.N;
-    S += smp * nc * d.H * d.ny * d.nx;
+    S += smp * nc * spec_size(d);
   }
   __shared__ cpx<T> lds[N * C::TX];
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
@@ -149,8 +149,7 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* _
   const int c = rest / d.ny;
   const int pp = xt * C::TX + col;
   const bool ok = pp < npair;
-  const long long plane = (long long)d.ny * d.nx;
-  const cpx<T>* src = S + (long long)c * d.H * plane + (long long)y * d.nx + 2 * (ok ? pp : 0);
+  const cpx<T>* src = S + (long long)c * spec_size(d) + 2 * (ok ? pp : 0);
   // all loads of this thread in flight before the first LDS store (H = N/2 + 1
   // half-spectrum planes, ceil(H/P) per thread)
   constexpr int H = N / 2 + 1, NL = (H + C::P - 1) / C::P;
@@ -159,7 +158,7 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* _
   for (int i = 0; i < NL; ++i) {
     const int mz = t + i * C::P;
     if (ok && mz < H) {
-      ab[i] = *reinterpret_cast<const cpx2<T>*>(src + (long long)mz * plane);
+      ab[i] = *reinterpret_cast<const cpx2<T>*>(src + zrow(d, mz, y) * d.nx);
     } else {
       ab[i].a = mk(T(0), T(0));
       ab[i].b = mk(T(0), T(0));
@@ -181,16 +180,31 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* _
   __syncthreads();
   fft_regs<T, N, C::E, 1, true>(v, t, lds, [col](int, int pos) { return pos * C::TX + col; }, tw);
   if (ok) {
-    T* dst = R + (long long)c * d.N + (long long)y * d.nx + 2 * pp;
+    T* dst = R + (long long)c * d.N + 2 * pp;
 #pragma unroll
-    for (int m = 0; m < C::E; ++m) *reinterpret_cast<cpx<T>*>(dst + (long long)(t + m * C::P) * plane) = v[0][m];
+    for (int m = 0; m < C::E; ++m) *reinterpret_cast<cpx<T>*>(dst + zrow(d, t + m * C::P, y) * d.nx) = v[0][m];
   }
 }
 
 // ---------------------------------------------------------------------------
 // x: forward transform of each contiguous x-line, Green operator per
-// frequency in registers, inverse transform; components take turns in LDS.
+// frequency in registers, inverse transform.
 // ---------------------------------------------------------------------------
+
+// x-line `line` of the z-blocked half spectrum (Hp ny lines per component) ->
+// its plane mz and row y; false for the padding planes mz >= H and beyond the
+// last line (then mz = y = 0).
+__device__ __forceinline__ bool xline_of(const Dims& d, int line, int& mz, int& my) {
+  mz = 0;
+  my = 0;
+  if (line >= d.Hp * d.ny) return false;
+  const int r = line >> d.zs;
+  const int z = ((r / d.ny) << d.zs) + (line & ((1 << d.zs) - 1));
+  if (z >= d.H) return false;
+  mz = z;
+  my = r % d.ny;
+  return true;
+}
 template <typename T, int N, int OP>
 __global__ __launch_bounds__((LineCfg<T, N, 3>::NT)) void k_xgreen3(cpx<T>* __restrict__ S, Dims d,
                                                                   const cpx<T>* __restrict__ tw, WaveTables<T> wt,
@@ -199,16 +213,17 @@ __global__ __launch_bounds__((LineCfg<T, N, 3>::NT)) void k_xgreen3(cpx<T>* __re
   using C = LineCfg<T, N, 3>;
   if (bt.active) {
     const long long smp = bt.active[blockIdx.y];
-    S += smp * 3 * d.H * d.ny * d.nx;
+    S += smp * 3 * spec_size(d);
     if (gs) g = gs[smp];
   }
   // the three components exchange through LDS together (51 KiB at 512):
   // a third of the barriers of taking turns
   __shared__ cpx<T> lds[3 * C::LPB * C::LINE];
   const int t = threadIdx.x % C::P, l = threadIdx.x / C::P;
-  const int nlines = d.H * d.ny;
+  const int nlines = d.Hp * d.ny;
   const int line = blockIdx.x * C::LPB + l;
-  const bool ok = line < nlines;
+  int mz, my;
+  const bool ok = xline_of(d, line, mz, my);
   const long long cs = (long long)nlines * N;
   cpx<T>* base = S + (long long)(ok ? line : 0) * N + t;
   cpx<T> v[3][C::E];
@@ -218,7 +233,6 @@ __global__ __launch_bounds__((LineCfg<T, N, 3>::NT)) void k_xgreen3(cpx<T>* __re
     for (int m = 0; m < C::E; ++m) v[c][m] = ok ? base[c * cs + m * C::P] : mk(T(0), T(0));
   const auto at = [l](int c, int pos) { return (c * C::LPB + l) * C::LINE + pad16(pos); };
   fft_regs<T, N, C::E, 3, false>(v, t, lds, at, tw);
-  const int mz = (ok ? line : 0) / d.ny, my = (ok ? line : 0) % d.ny;
 #pragma unroll
   for (int m = 0; m < C::E; ++m) {
     cpx<T> b[3] = {v[0][m], v[1][m], v[2][m]};
@@ -242,9 +256,10 @@ __global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xgreen6(cpx<T>* __re
   using C = LineCfg<T, N, 6>;
   __shared__ cpx<T> lds[C::LPB * C::LINE];
   const int t = threadIdx.x % C::P, l = threadIdx.x / C::P;
-  const int nlines = d.H * d.ny;
+  const int nlines = d.Hp * d.ny;
   const int line = blockIdx.x * C::LPB + l;
-  const bool ok = line < nlines;
+  int mz, my;
+  const bool ok = xline_of(d, line, mz, my);
   const long long cs = (long long)nlines * N;
   cpx<T>* base = S + (long long)(ok ? line : 0) * N + t;
   cpx<T> v[6][C::E];
@@ -254,7 +269,6 @@ __global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xgreen6(cpx<T>* __re
     for (int m = 0; m < C::E; ++m) v[c][m] = ok ? base[c * cs + m * C::P] : mk(T(0), T(0));
   const auto at = [l](int, int pos) { return l * C::LINE + pad16(pos); };
   fft_regs<T, N, C::E, 6, false, true>(v, t, lds, at, tw);
-  const int mz = (ok ? line : 0) / d.ny, my = (ok ? line : 0) % d.ny;
 #pragma unroll
   for (int m = 0; m < C::E; ++m) {
     cpx<T> tv[6];
@@ -281,9 +295,10 @@ __global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xeta6(const cpx<T>* 
   __shared__ cpx<T> lds[C::LPB * C::LINE];
   __shared__ double red[16];
   const int t = threadIdx.x % C::P, l = threadIdx.x / C::P;
-  const int nlines = d.H * d.ny;
+  const int nlines = d.Hp * d.ny;
   const int line = blockIdx.x * C::LPB + l;
-  const bool ok = line < nlines;
+  int mz, my;
+  const bool ok = xline_of(d, line, mz, my);
   const long long cs = (long long)nlines * N;
   const cpx<T>* base = S + (long long)(ok ? line : 0) * N + t;
   cpx<T> v[6][C::E];
@@ -293,7 +308,6 @@ __global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xeta6(const cpx<T>* 
     for (int m = 0; m < C::E; ++m) v[c][m] = ok ? base[c * cs + m * C::P] : mk(T(0), T(0));
   const auto at = [l](int, int pos) { return l * C::LINE + pad16(pos); };
   fft_regs<T, N, C::E, 6, false, true>(v, t, lds, at, tw);
-  const int mz = (ok ? line : 0) / d.ny, my = (ok ? line : 0) % d.ny;
   double acc[1] = {0.0};
   if (ok) {
 #pragma unroll
@@ -327,7 +341,7 @@ static bool dispatch_length(int n, F&& f) {
 template <typename T, int N>
 inline int x_blocks(const Dims& d, int nc) {
   const int lpb = nc == 3 ? LineCfg<T, N, 3>::LPB : LineCfg<T, N, 6>::LPB;
-  return (d.H * d.ny + lpb - 1) / lpb;
+  return (d.Hp * d.ny + lpb - 1) / lpb;
 }
 
 }  // namespace fe

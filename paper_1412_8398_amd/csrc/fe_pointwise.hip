@@ -242,7 +242,7 @@ __global__ __launch_bounds__(Tile<TC>::DX * Tile<TC>::DY) void k_div(const TS* _
       }
     }
     if (zz >= z0 && own) {
-      const long long c = ((long long)z * ny + y) * nx + x;
+      const long long c = zidx(d, z, y, x);  // corner arrays: z-blocked transform layout
       TC Dt[3], Ds[3];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(Tile<TC>::DX * Tile<TC>::DY) void k_div(const TS* _
 // fused strain update and divergence (WP, ROT): from U (the inverse transform
 // of iteration k) and eps^k, compute eps^(k+1) and, in the same walk along z,
 // the divergences of tau(eps^(k+1)) and sigma(eps^(k+1)) with eta's partial
-// sums -- the work of k_grad_update followed by k_div without writing eps^(k+1)
+// sums -- a strain update followed by k_div without writing eps^(k+1)
 // and reading it back.  Same tiles, walk and reductions as k_div.  The voxels
 // of the -x, -y halo are recomputed (their owner tile writes them), so eps^k
 // and eps^(k+1) must be different buffers.
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const 
       const int idx = threadIdx.x + q * NT;
       if (idx < UR) {
         const int i = idx % (DX + 2), j = idx / (DX + 2);
-        const long long c = ((long long)z * ny + pmod(y0 - 1 + j, ny)) * nx + pmod(x0 - 1 + i, nx);
+        const long long c = zidx(d, z, pmod(y0 - 1 + j, ny), pmod(x0 - 1 + i, nx));  // z-blocked U
 #pragma unroll
         for (int k = 0; k < 3; ++k) ureg[q][k] = U[k * N + c];
       }
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const 
       }
     }
     if (zz >= z0 && own) {
-      const long long c = ((long long)z * ny + y) * nx + x;
+      const long long c = zidx(d, z, y, x);  // corner arrays: z-blocked transform layout
       T Dt[3], Ds[3];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
@@ -547,68 +547,6 @@ int div_partial_count(Dims d) {
 // AS (eq. (16)): eps <- eps + 2 kappa0/(kappa+kappa0) sph(e - eps) + 2 mu0/(mu+mu0) dev(e - eps).
 // --------------------------------------------------------------------------
 
-// With rfield non-null the applied strain is the field rfield (6 planes)
-// instead of the constant eps_bar: the update of a correction whose anchor
-// strain has the strain residual rfield.
-template <typename T, int OP, bool AS>
-__global__ __launch_bounds__(256) void k_grad_update(const T* __restrict__ U, T* __restrict__ eps,
-                                                     const uint8_t* __restrict__ phase,
-                                                     const PhaseCoef<T>* __restrict__ coef, GreenConst<T> g,
-                                                     const T* __restrict__ rfield, Dims d, Batch bt,
-                                                     const GreenConst<T>* __restrict__ gs) {
-  const long long N = d.N;
-  {
-    const long long smp = bt.active ? bt.active[blockIdx.y] : 0;
-    U += smp * 3 * N;
-    eps += smp * 6 * N;
-    phase += smp * N;
-    coef += smp * bt.ncoef;
-    if (rfield) rfield += smp * 6 * N;
-    if (gs) g = gs[smp];
-  }
-  const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const long long b0 = xcd_block(blockIdx.x, gridDim.x);
-  for (long long v = b0 * blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(v % nx);
-    const int y = (int)((v / nx) % ny);
-    const int z = (int)(v / ((long long)nx * ny));
-    T gr[3][3];  // gr[i][j] = d_i U_j
-    if (OP == OP_ROT) {
-      T u[8][3];
-#pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const long long c = ((long long)wrap(z + (a >> 2), nz) * ny + wrap(y + ((a >> 1) & 1), ny)) * nx +
-                            wrap(x + (a & 1), nx);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) u[a][k] = U[k * N + c];
-      }
-      grad_rot(u, gr);
-    } else {
-      const T u0[3] = {U[v], U[N + v], U[2 * N + v]};
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int xp = i == 0 ? wrap(x + 1, nx) : x;
-        const int yp = i == 1 ? wrap(y + 1, ny) : y;
-        const int zp = i == 2 ? wrap(z + 1, nz) : z;
-        const long long c = ((long long)zp * ny + yp) * nx + xp;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) gr[i][j] = U[j * N + c] - u0[j];
-      }
-    }
-    T base[6], cur[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      base[k] = rfield ? rfield[k * N + v] : g.macro[k];
-      cur[k] = AS ? eps[k * N + v] : T(0);
-    }
-    const PhaseCoef<T> pc = coef[phase[v]];
-    T e[6];
-    strain_update<T, AS>(gr, base, cur, pc, e);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) eps[k * N + v] = e[k];
-  }
-}
-
 // Strain residual of an anchor strain in float64 arithmetic:
 // r = eps_bar + sym grad_h U - eps (U from the float64 transforms of the
 // divergence of (C - C0):eps), stored in the anchor's precision.
@@ -630,7 +568,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ U, 
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
         const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-        const long long c = ((long long)wrap(z + az, nz) * ny + wrap(y + ay, ny)) * nx + wrap(x + ax, nx);
+        const long long c = zidx(d, wrap(z + az, nz), wrap(y + ay, ny), wrap(x + ax, nx));  // z-blocked U
         const double u[3] = {U[c], U[N + c], U[2 * N + c]};
         const double sg[3] = {ax ? 1.0 : -1.0, ay ? 1.0 : -1.0, az ? 1.0 : -1.0};
 #pragma unroll
@@ -643,13 +581,14 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ U, 
 #pragma unroll
         for (int j = 0; j < 3; ++j) gr[i][j] *= 0.25;
     } else {
-      const double u0[3] = {U[v], U[N + v], U[2 * N + v]};
+      const long long c0 = zidx(d, z, y, x);  // z-blocked U
+      const double u0[3] = {U[c0], U[N + c0], U[2 * N + c0]};
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const int xp = i == 0 ? wrap(x + 1, nx) : x;
         const int yp = i == 1 ? wrap(y + 1, ny) : y;
         const int zp = i == 2 ? wrap(z + 1, nz) : z;
-        const long long c = ((long long)zp * ny + yp) * nx + xp;
+        const long long c = zidx(d, zp, yp, xp);
 #pragma unroll
         for (int j = 0; j < 3; ++j) gr[i][j] = U[j * N + c] - u0[j];
       }
@@ -675,7 +614,8 @@ __global__ void k_axpy(T* __restrict__ y, const T* __restrict__ x, long long n) 
 template <typename T>
 __global__ __launch_bounds__(256) void k_tau6(const T* __restrict__ eps, const uint8_t* __restrict__ phase,
                                               const PhaseCoef<T>* __restrict__ coef, T* __restrict__ out,
-                                              int write_sigma, double* __restrict__ partials, long long N) {
+                                              int write_sigma, double* __restrict__ partials, Dims d) {
+  const long long N = d.N;
   __shared__ double red[7 * 16];
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
@@ -685,9 +625,10 @@ __global__ __launch_bounds__(256) void k_tau6(const T* __restrict__ eps, const u
     T s[6], t[6];
     iso_apply(pc.lam, pc.mu, e, s);
     iso_apply(pc.dlam, pc.dmu, e, t);
+    const long long vb = zblk(d, v);  // the transform input: z-blocked
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      out[k * N + v] = write_sigma ? s[k] : t[k];
+      out[k * N + vb] = write_sigma ? s[k] : t[k];
       acc[1 + k] += double(s[k]);
     }
   }
@@ -703,15 +644,17 @@ __global__ __launch_bounds__(256) void k_tau6(const T* __restrict__ eps, const u
 template <typename T, bool AS>
 __global__ __launch_bounds__(256) void k_update6(const T* __restrict__ e, T* __restrict__ eps,
                                                  const uint8_t* __restrict__ phase,
-                                                 const PhaseCoef<T>* __restrict__ coef, long long N) {
+                                                 const PhaseCoef<T>* __restrict__ coef, Dims d) {
+  const long long N = d.N;
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+    const long long vb = zblk(d, v);  // e: the inverse transform output, z-blocked
     if (AS) {
       const PhaseCoef<T> pc = coef[phase[v]];
       T cur[6], dd[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         cur[k] = eps[k * N + v];
-        dd[k] = e[k * N + v] - cur[k];
+        dd[k] = e[k * N + vb] - cur[k];
       }
       const T sph = (dd[0] + dd[1] + dd[2]) * T(1.0 / 3.0);
 #pragma unroll
@@ -720,7 +663,7 @@ __global__ __launch_bounds__(256) void k_update6(const T* __restrict__ e, T* __r
       for (int k = 3; k < 6; ++k) eps[k * N + v] = cur[k] + pc.am * dd[k];
     } else {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) eps[k * N + v] = e[k * N + v];
+      for (int k = 0; k < 6; ++k) eps[k * N + v] = e[k * N + vb];
     }
   }
 }
@@ -849,24 +792,6 @@ int launch_div64(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* c
   return gd.blocks;
 }
 
-template <typename T>
-void Launch<T>::grad_update(const T* U, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, GreenConst<T> g,
-                            const T* rfield, Dims d, int op, int accelerated, hipStream_t s, Batch bt,
-                            const GreenConst<T>* gs, int nsamp) {
-  const dim3 gr(grid_for(d.N, 1 << 20), nsamp), bl(kThreads);
-  if (op == OP_ROT) {
-    if (accelerated)
-      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, true>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d, bt, gs);
-    else
-      hipLaunchKernelGGL((k_grad_update<T, OP_ROT, false>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d, bt, gs);
-  } else {
-    if (accelerated)
-      hipLaunchKernelGGL((k_grad_update<T, OP_WP, true>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d, bt, gs);
-    else
-      hipLaunchKernelGGL((k_grad_update<T, OP_WP, false>), gr, bl, 0, s, U, eps, phase, coef, g, rfield, d, bt, gs);
-  }
-}
-
 template <typename TE>
 void launch_residual(const double* U, const TE* eps, GreenConst<double> g, TE* r, Dims d, int op, hipStream_t s) {
   const dim3 gr(grid_for(d.N, 1 << 20)), bl(kThreads);
@@ -885,7 +810,7 @@ template <typename T>
 void Launch<T>::tau6(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* out, int write_sigma,
                      double* partials, int nblocks, Dims d, hipStream_t s) {
   hipLaunchKernelGGL((k_tau6<T>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef, out, write_sigma, partials,
-                     d.N);
+                     d);
 }
 
 template <typename T>
@@ -893,10 +818,10 @@ void Launch<T>::update6(const T* e, T* eps, const uint8_t* phase, const PhaseCoe
                         hipStream_t s) {
   if (accelerated)
     hipLaunchKernelGGL((k_update6<T, true>), dim3(grid_for(d.N, 1 << 20)), dim3(kThreads), 0, s, e, eps, phase, coef,
-                       d.N);
+                       d);
   else
     hipLaunchKernelGGL((k_update6<T, false>), dim3(grid_for(d.N, 1 << 20)), dim3(kThreads), 0, s, e, eps, phase,
-                       coef, d.N);
+                       coef, d);
 }
 
 template <typename T>
@@ -920,9 +845,6 @@ void launch_reduce(const double* partials, int nblocks, int nv, double* out, hip
   template int Launch<T>::update_div(const T*, const T*, T*, const uint8_t*, const PhaseCoef<T>*, GreenConst<T>, \
                                      const T*, T*, const T*, double*, Dims, int, int, hipStream_t, Batch,         \
                                      const GreenConst<T>*, int);                                                  \
-  template void Launch<T>::grad_update(const T*, T*, const uint8_t*, const PhaseCoef<T>*, GreenConst<T>,  \
-                                       const T*, Dims, int, int, hipStream_t, Batch, const GreenConst<T>*, \
-                                       int);                                                              \
   template void Launch<T>::tau6(const T*, const uint8_t*, const PhaseCoef<T>*, T*, int, double*, int, Dims, \
                                 hipStream_t);                                                             \
   template void Launch<T>::update6(const T*, T*, const uint8_t*, const PhaseCoef<T>*, Dims, int, hipStream_t); \
