@@ -8,7 +8,7 @@ void Launch<T>::yfft(cpx<T>* S, int ncomp, Dims d, const cpx<T>* twy, int invers
                      int nsamp) {
   dispatch_length(d.ny, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
-    using C = StridedCfg<T, N>;
+    using C = StridedCfg<T, N, true>;
     const int ntx = (d.nx + C::TX - 1) / C::TX;
     const dim3 grid(ntx * d.H * ncomp, nsamp), block(C::NT);
     if (inverse)

@@ -20,11 +20,15 @@ constexpr int imax(int a, int b) { return a > b ? a : b; }
 
 // Strided passes: TX adjacent x-columns per workgroup, P = N/E threads per
 // column, E elements per thread; 256 threads unless the LDS tile caps TX.
-template <typename T, int N>
+template <typename T, int N, bool YPASS = false>
 struct StridedCfg {
   static constexpr int E = e_strided(N);
   static constexpr int P = N / E;
-  static constexpr int TX = imax(1, imin(256 / P, lds_budget<T>() / N));
+  // long y columns: 512 threads and up to 128 KiB of LDS keep 16 columns
+  // (128-byte rows in float) per workgroup (measured: faster for y at 1024,
+  // slower for the z passes, whose 64-byte halves pair up in L2 anyway)
+  static constexpr bool BIG = YPASS && N >= 768;
+  static constexpr int TX = imax(1, imin((BIG ? 512 : 256) / P, (BIG ? 2 : 1) * lds_budget<T>() / N));
   static constexpr int NT = TX * P;
 };
 
@@ -49,9 +53,9 @@ struct alignas(4 * sizeof(T)) cpx2 {
 // y: complex transform of the half spectrum along y, in place
 // ---------------------------------------------------------------------------
 template <typename T, int N, bool INV>
-__global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_ypass(cpx<T>* __restrict__ S, Dims d,
-                                                                const cpx<T>* __restrict__ tw, Batch bt) {
-  using C = StridedCfg<T, N>;
+__global__ __launch_bounds__((StridedCfg<T, N, true>::NT)) void k_ypass(cpx<T>* __restrict__ S, Dims d,
+                                                                      const cpx<T>* __restrict__ tw, Batch bt) {
+  using C = StridedCfg<T, N, true>;
   if (bt.active) S += (long long)bt.active[blockIdx.y] * (gridDim.x / (((d.nx + C::TX - 1) / C::TX) * d.H)) * spec_size(d);
   __shared__ cpx<T> lds[N * C::TX];
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;

@@ -514,7 +514,7 @@ __global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const 
 }
 
 // Tiling of the divergence walk: one corner tile and z chunk per workgroup,
-// z cut into chunks of at least 8 planes so that a launch has about 2M
+// z cut into chunks of 8 to 64 planes so that a launch has at least about 2M
 // threads (several generations of resident workgroups on 256 CUs).
 struct DivGrid {
   int blocks, zchunk;
@@ -526,6 +526,11 @@ static DivGrid div_grid(const Dims& d) {
   const int bxy = ntx * nty;
   const int target = (1 << 21) / (DX * DY);
   int nch = (target + bxy - 1) / bxy;
+  // chunks of at most 64 planes: neighbouring tiles that start together stay
+  // within a few planes of each other, so the halo lines they share are still
+  // in L2 when the second one reads them (1024^3: 56 -> 50 B/voxel fetched)
+  if (nch < d.nz / 64) nch = d.nz / 64;
+  if (nch > kMaxReduceBlocks / bxy) nch = kMaxReduceBlocks / bxy;
   if (nch > d.nz / 8) nch = d.nz / 8;  // chunks of at least 8 planes (one halo plane each)
   if (nch < 1) nch = 1;
   const int zchunk = (d.nz + nch - 1) / nch;
