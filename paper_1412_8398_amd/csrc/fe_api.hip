@@ -663,9 +663,19 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
         nb_D = Launch<T>::update_div(R, it, nxt, phase, coef, g, rf, R2, dbase, p->partials, d, p->op, accel, s);
       });
     };
+    // Queue ahead only while this check is unlikely to end the run: when the
+    // eta just read may reach tol (the last ratio extrapolated once, with a
+    // factor 3 of margin) the queued iteration would be dropped, costing a
+    // whole iteration instead of the host round trip it hides.
+    bool ahead = p->displacement && k < max_iter;
+    if (ahead && !hist.empty()) {
+      const size_t nh = hist.size();
+      const double r = nh >= 2 && hist[nh - 2] > 0.0 ? hist[nh - 1] / hist[nh - 2] : 1.0;
+      if (hist[nh - 1] * std::min(r, 1.0) <= 3.0 * tol) ahead = false;
+    }
     if (check) {
       HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
-      if (p->displacement && k < max_iter) {
+      if (ahead) {
         HIP_TRY(hipEventRecord(p->evc, s));
         enqueue_passes();
         queued = true;
