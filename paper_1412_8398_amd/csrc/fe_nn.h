@@ -51,7 +51,13 @@ constexpr int TX = 16, TY = 4, TZ = 4;
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HV = HX * HY * HZ;
 
 __host__ __device__ constexpr int conv_cch(int cin) { return cin % 32 == 0 ? 32 : (cin % 16 == 0 ? 16 : 8); }
-__host__ __device__ constexpr int conv_ksteps(int cin) { return (27 + 32 / conv_cch(cin) - 1) / (32 / conv_cch(cin)); }
+// Reduction steps of 32 per channel chunk.  The 9 (dz, dx) tap columns are
+// dealt to the 32 / cch tap slots of a step in groups; each group takes 3
+// steps, dy = -1, 0, +1, so a wavefront keeps a window of TY + 2 input rows
+// in registers and reads each from LDS once per group (instead of once per
+// output row and step).  Slots beyond the 9 columns carry zero weights.
+__host__ __device__ constexpr int conv_groups(int cin) { return (9 + 32 / conv_cch(cin) - 1) / (32 / conv_cch(cin)); }
+__host__ __device__ constexpr int conv_ksteps(int cin) { return 3 * conv_groups(cin); }
 // packed weights: [chunk][kstep][out tile][lane] x 8 bf16 (16 bytes)
 __host__ __device__ constexpr long long packed_elems(int cin, int cout) {
   return (long long)(cin / conv_cch(cin)) * conv_ksteps(cin) * (cout / 16) * 64 * 8;

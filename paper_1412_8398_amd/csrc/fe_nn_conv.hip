@@ -64,6 +64,7 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
                                                const u32x4* __restrict__ W, const float* __restrict__ bias,
                                                uint16_t* __restrict__ Y, Grid3 g) {
   constexpr int CCH = conv_cch(CIN), NCH = CIN / CCH, TPK = 32 / CCH, KS = conv_ksteps(CIN), MT = COUT / 16;
+  constexpr int NG = conv_groups(CIN);
   constexpr int PIECES = CCH / 8;
   __shared__ u32x4 lds[HV * PIECES];  // [halo voxel][8-channel piece]
   const TileCoord tc = tile_of(blockIdx.x, g);
@@ -76,8 +77,8 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
 #pragma unroll
     for (int r = 0; r < TY; ++r) acc[mt][r] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // this lane's reduction group: tap within the k step and channel piece
-  const int tap_in = (grp * 8) / CCH, pc = ((grp * 8) % CCH) / 8;
+  // this lane's reduction group: tap slot within the k step and channel piece
+  const int slot = (grp * 8) / CCH, pc = ((grp * 8) % CCH) / 8;
 
   for (int ch = 0; ch < NCH; ++ch) {
     if (ch) __syncthreads();
@@ -91,19 +92,23 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
       lds[i] = v;
     }
     __syncthreads();
-    for (int ks = 0; ks < KS; ++ks) {
-      int tap = ks * TPK + tap_in;
-      if (tap > 26) tap = 13;  // padding tap: zero weights, any finite input
-      const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-      u32x4 bfr[TY];
+    for (int gi = 0; gi < NG; ++gi) {
+      int col = gi * TPK + slot;  // (dz, dx) column of this lane's taps
+      if (col > 8) col = 4;       // padding slot: zero weights, any finite input
+      const int dz = col / 3 - 1, dx = col % 3 - 1;
+      // halo rows 0 .. TY+1 of this column: output row r, dy = kk - 1 reads row r + kk
+      u32x4 fr[TY + 2];
 #pragma unroll
-      for (int r = 0; r < TY; ++r) bfr[r] = lds[(((w + dz + 1) * HY + (r + dy + 1)) * HX + (j + dx + 1)) * PIECES + pc];
-      const u32x4* wp = W + (long long)(ch * KS + ks) * MT * 64 + lane;
+      for (int rr = 0; rr < TY + 2; ++rr) fr[rr] = lds[(((w + dz + 1) * HY + rr) * HX + (j + dx + 1)) * PIECES + pc];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const u32x4 a = wp[mt * 64];
+      for (int kk = 0; kk < 3; ++kk) {
+        const u32x4* wp = W + (long long)(ch * KS + 3 * gi + kk) * MT * 64 + lane;
 #pragma unroll
-        for (int r = 0; r < TY; ++r) acc[mt][r] = mfma(a, bfr[r], acc[mt][r]);
+        for (int mt = 0; mt < MT; ++mt) {
+          const u32x4 a = wp[mt * 64];
+#pragma unroll
+          for (int r = 0; r < TY; ++r) acc[mt][r] = mfma(a, fr[r + kk], acc[mt][r]);
+        }
       }
     }
   }

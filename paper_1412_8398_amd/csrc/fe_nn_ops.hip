@@ -71,7 +71,11 @@ __global__ void k_pack(const float* __restrict__ w, int cin, int cout, int flip,
   rest /= MT;
   const int ks = rest % KS, ch = rest / KS;
   const int c = lane & 15, q = lane >> 4;
-  const int tap = ks * TPK + (8 * q) / CCH, c0 = ch * CCH + (8 * q) % CCH, o = mt * 16 + c;
+  // step ks = 3 gi + kk: slot (8q)/CCH takes the (dz, dx) column gi TPK + slot
+  // at dy = kk - 1 (the order of the convolution kernel's register window)
+  const int col = (ks / 3) * TPK + (8 * q) / CCH, kk = ks % 3;
+  const int tap = col < 9 ? (col / 3) * 9 + kk * 3 + col % 3 : 27;
+  const int c0 = ch * CCH + (8 * q) % CCH, o = mt * 16 + c;
   float f[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
