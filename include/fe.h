@@ -117,9 +117,11 @@ typedef struct fe_plan fe_plan;
 void fe_plan_options_default(fe_plan_options* opt);
 
 /*
- * Create a plan: validates the grid (each of nx, ny, nz even, of the form
- * 2^a 3^b, between 4 and 1024), allocates the device workspace and builds
- * the FP64 twiddle and wave-vector tables.  opt may be NULL (defaults).
+ * Create a plan: validates the grid (each of nx, ny, nz of the form 2^a or
+ * 3*2^a, between 4 and 1024; nz may also be 1: a one-plane cell, the 2D
+ * problem in plane strain, where every operator takes its 2D form, q3 = 0),
+ * allocates the device workspace and builds the FP64 twiddle and
+ * wave-vector tables.  opt may be NULL (defaults).
  * Errors: FE_ERR_INVALID_ARG (bad enum/size), FE_ERR_UNSUPPORTED (size outside
  * the supported set), FE_ERR_OOM, FE_ERR_DEVICE.
  */

@@ -236,8 +236,8 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
   const int n[3] = {g.nx, g.ny, g.nz};
   for (int a = 0; a < 3; ++a) {
     if (n[a] <= 0) return fail(FE_ERR_INVALID_ARG, "grid dimension %d is %d", a, n[a]);
-    if (!supported_length(n[a]))
-      return fail(FE_ERR_UNSUPPORTED, "grid dimension %d = %d: need 2^a or 3*2^a in [4, 1024]", a, n[a]);
+    if (!(a == 2 ? supported_z_length(n[a]) : supported_length(n[a])))
+      return fail(FE_ERR_UNSUPPORTED, "grid dimension %d = %d: need 2^a or 3*2^a in [4, 1024] (nz: or 1)", a, n[a]);
   }
 
   fe_plan* p = new fe_plan();
@@ -1178,7 +1178,8 @@ extern "C" fe_status fe_solve_batched(fe_discretization disc, fe_scheme scheme, 
     const fe_grid& g = desc->grids[i];
     const int n[3] = {g.nx, g.ny, g.nz};
     for (int a = 0; a < 3; ++a)
-      if (!supported_length(n[a])) return fail(FE_ERR_UNSUPPORTED, "sample %d: grid dimension %d = %d", i, a, n[a]);
+      if (!(a == 2 ? supported_z_length(n[a]) : supported_length(n[a])))
+        return fail(FE_ERR_UNSUPPORTED, "sample %d: grid dimension %d = %d", i, a, n[a]);
     if (!desc->phase[i]) return fail(FE_ERR_INVALID_ARG, "sample %d: phase is NULL", i);
     fe_status st = validate_materials(desc->materials[i]);
     if (st != FE_OK) return st;

@@ -202,5 +202,7 @@ __host__ __device__ constexpr bool supported_length(int n) {
   return n == 4 || n == 6 || n == 8 || n == 12 || n == 16 || n == 24 || n == 32 || n == 48 || n == 64 ||
          n == 96 || n == 128 || n == 192 || n == 256 || n == 384 || n == 512 || n == 768 || n == 1024;
 }
+// z lengths: the above, and 1 (a one-plane cell, a 2D problem in plane strain)
+__host__ __device__ constexpr bool supported_z_length(int n) { return n == 1 || supported_length(n); }
 
 }  // namespace fe

@@ -6,7 +6,7 @@ namespace fe {
 template <typename T>
 void Launch<T>::zr2c(const T* R, cpx<T>* S, int ncomp, Dims d, const cpx<T>* twz, hipStream_t s, Batch bt,
                      int nsamp) {
-  dispatch_length(d.nz, [&](auto NC) {
+  dispatch_z_length(d.nz, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
     using C = StridedCfg<T, N>;
     const int ntx = (d.nx / 2 + C::TX - 1) / C::TX;
@@ -17,7 +17,7 @@ void Launch<T>::zr2c(const T* R, cpx<T>* S, int ncomp, Dims d, const cpx<T>* twz
 template <typename T>
 void Launch<T>::zc2r(const cpx<T>* S, T* R, int ncomp, Dims d, const cpx<T>* twz, hipStream_t s, Batch bt,
                      int nsamp) {
-  dispatch_length(d.nz, [&](auto NC) {
+  dispatch_z_length(d.nz, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
     using C = StridedCfg<T, N>;
     const int ntx = (d.nx / 2 + C::TX - 1) / C::TX;

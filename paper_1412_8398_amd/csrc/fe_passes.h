@@ -341,6 +341,15 @@ static bool dispatch_length(int n, F&& f) {
   }
   return false;
 }
+// z passes: the lengths above and 1 (one-plane cells)
+template <class F>
+static bool dispatch_z_length(int n, F&& f) {
+  if (n == 1) {
+    f(std::integral_constant<int, 1>());
+    return true;
+  }
+  return dispatch_length(n, f);
+}
 
 template <typename T, int N>
 inline int x_blocks(const Dims& d, int nc) {

@@ -128,6 +128,35 @@ def test_long_z_parity(shape):
     assert _rel(eps32, ref) < 5e-5
 
 
+@pytest.mark.parametrize("scheme", ["DS", "AS"])
+@pytest.mark.parametrize("op", ["MS", "W", "R", "C"])
+def test_one_plane_cells_parity_fp64(op, scheme):
+    """nz = 1: the 2D problem in plane strain (every operator at q3 = 0),
+    element by element against the oracle at equal iteration index."""
+    for shape in ((1, 16, 24), (1, 32, 12)):
+        phase, E, nu = _three_phase(shape, seed=21)
+        k = 4
+        ref = O.solve(phase, E, nu, MACRO, op=op, scheme=scheme, tol=1e-300, max_iter=k)
+        res, eps = _run(phase, E, nu, MACRO, op, scheme, "fp64", k=k)
+        assert _rel(eps, O.tensor_to_voigt(ref.eps)) < 1e-12
+        assert np.allclose(res.eta_history, ref.eta_history, rtol=1e-10, atol=1e-14)
+
+
+def test_one_plane_cell_converges_with_the_oracle():
+    """A 2D cell solved to 1e-10 (float64 and float32 with re-anchoring):
+    the oracle's iteration count and mean stress."""
+    shape = (1, 64, 64)
+    phase, E, nu = _three_phase(shape, seed=22)
+    ref = O.solve(phase, E, nu, MACRO, op="R", scheme="AS", tol=1e-10, max_iter=2000)
+    res, eps = _run(phase, E, nu, MACRO, "R", "AS", "fp64", tol=1e-10, max_iter=2000)
+    assert res.status == fe.FE_OK and res.iterations == ref.iterations
+    want = O.tensor_to_voigt(ref.mean_stress)
+    assert np.allclose(res.mean_stress, want, rtol=1e-10, atol=1e-12)
+    r32, _ = _run(phase, E, nu, MACRO, "R", "AS", "fp32", tol=1e-7, max_iter=2000)
+    assert r32.status == fe.FE_OK and r32.eta_verify_fp64 <= 1.2e-7
+    assert np.allclose(r32.mean_stress, want, rtol=1e-5, atol=1e-6)
+
+
 def test_warm_start_parity_fp64(rng):
     shape = (16, 24, 12)
     phase, E, nu = _three_phase(shape, seed=3)
