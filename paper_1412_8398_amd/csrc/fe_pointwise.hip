@@ -159,16 +159,27 @@ struct Tile<double> {
   static constexpr int DX = 32, DY = 8;
 };
 
+// Workgroup barrier that orders LDS accesses only: global loads issued before
+// it stay in flight (they prefetch the next plane).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Optional outputs/inputs (null to skip): Dtau receives the divergence of tau
 // (type TD), Dsig the divergence of sigma (type TS), and Dsig_base is added to
 // the divergence of sigma before it is squared for eta (the divergence of an
-// anchor strain when iterating on a correction).
+// anchor strain when iterating on a correction).  The strain and phase of the
+// next voxel plane are prefetched into registers while the current plane's
+// divergence is formed; tau and sigma sit in LDS component-major.
 template <typename TS, typename TC, typename TD, int OP>
 __global__ __launch_bounds__(Tile<TC>::DX * Tile<TC>::DY) void k_div(const TS* __restrict__ eps, const uint8_t* __restrict__ phase,
                                                  const PhaseCoef<TC>* __restrict__ coef, TD* __restrict__ Dtau,
                                                  TS* __restrict__ Dsig, const TS* __restrict__ Dsig_base,
                                                  double* __restrict__ partials, Dims d, int zchunk, Batch bt) {
   constexpr int DX = Tile<TC>::DX, DY = Tile<TC>::DY;
+  constexpr int ER = (DX + 1) * (DY + 1), NT = DX * DY, ES = (ER + NT - 1) / NT;
   {
     const long long smp = bt.active ? bt.active[blockIdx.y] : 0;
     eps += smp * 6 * d.N;
@@ -179,8 +190,8 @@ __global__ __launch_bounds__(Tile<TC>::DX * Tile<TC>::DY) void k_div(const TS* _
     if (Dsig_base) Dsig_base += smp * 3 * d.N;
     partials += smp * gridDim.x * 7;
   }
-  __shared__ TC st[DY + 1][DX + 1][6];
-  __shared__ TC ss[DY + 1][DX + 1][6];
+  __shared__ TC st[6][DY + 1][DX + 1];
+  __shared__ TC ss[6][DY + 1][DX + 1];
   __shared__ double red[7 * 16];
   const long long N = d.N;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
@@ -195,28 +206,47 @@ __global__ __launch_bounds__(Tile<TC>::DX * Tile<TC>::DY) void k_div(const TS* _
   const int tx = threadIdx.x % DX, ty = threadIdx.x / DX;
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x < nx && y < ny;
+  TS ereg[ES][6];
+  int preg[ES];
+  auto fetch_e = [&](int zz) {
+    const int z = pmod(zz, nz);
+#pragma unroll
+    for (int q = 0; q < ES; ++q) {
+      const int idx = threadIdx.x + q * NT;
+      if (idx < ER) {
+        const int i = idx % (DX + 1), j = idx / (DX + 1);
+        const long long v = ((long long)z * ny + pmod(y0 - 1 + j, ny)) * nx + pmod(x0 - 1 + i, nx);
+        preg[q] = phase[v];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ereg[q][k] = eps[k * N + v];
+      }
+    }
+  };
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   TC pt[3] = {0, 0, 0}, qt[3] = {0, 0, 0}, ps[3] = {0, 0, 0}, qs[3] = {0, 0, 0};
+  fetch_e(z0 - 1);
   for (int zz = z0 - 1; zz < z1; ++zz) {
     const int z = zz < 0 ? zz + nz : zz;
-    for (int idx = threadIdx.x; idx < (DX + 1) * (DY + 1); idx += DX * DY) {
+#pragma unroll
+    for (int q = 0; q < ES; ++q) {
+      const int idx = threadIdx.x + q * NT;
+      if (idx >= ER) continue;
       const int i = idx % (DX + 1), j = idx / (DX + 1);
-      const int xv = pmod(x0 - 1 + i, nx), yv = pmod(y0 - 1 + j, ny);
-      const long long v = ((long long)z * ny + yv) * nx + xv;
       TC e[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] = TC(eps[k * N + v]);
-      const PhaseCoef<TC> pc = coef[phase[v]];
+      for (int k = 0; k < 6; ++k) e[k] = TC(ereg[q][k]);
+      const PhaseCoef<TC> pc = coef[preg[q]];
       TC t[6], sg[6];
       iso_apply(pc.dlam, pc.dmu, e, t);
       iso_apply(pc.lam, pc.mu, e, sg);
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        st[j][i][k] = t[k];
-        ss[j][i][k] = sg[k];
+        st[k][j][i] = t[k];
+        ss[k][j][i] = sg[k];
       }
     }
-    __syncthreads();
+    if (zz + 1 < z1) fetch_e(zz + 1);  // in flight during this plane's divergence
+    lds_barrier();
     // voxel c - a for a in {0,1}^2 in the plane: (tx+1-ax, ty+1-ay)
     TC Pt[3], Qt[3], Ps[3], Qs[3];
 #pragma unroll
@@ -224,21 +254,21 @@ __global__ __launch_bounds__(Tile<TC>::DX * Tile<TC>::DY) void k_div(const TS* _
       const int cx = voigt_of(0, j), cy = voigt_of(1, j), cz = voigt_of(2, j);
       if (OP == OP_ROT) {
         // f(c), f(c-ex), f(c-ey), f(c-ex-ey)
-        const TC ax0 = st[ty + 1][tx + 1][cx], ax1 = st[ty + 1][tx][cx], ax2 = st[ty][tx + 1][cx], ax3 = st[ty][tx][cx];
-        const TC ay0 = st[ty + 1][tx + 1][cy], ay1 = st[ty + 1][tx][cy], ay2 = st[ty][tx + 1][cy], ay3 = st[ty][tx][cy];
-        const TC az0 = st[ty + 1][tx + 1][cz], az1 = st[ty + 1][tx][cz], az2 = st[ty][tx + 1][cz], az3 = st[ty][tx][cz];
+        const TC ax0 = st[cx][ty + 1][tx + 1], ax1 = st[cx][ty + 1][tx], ax2 = st[cx][ty][tx + 1], ax3 = st[cx][ty][tx];
+        const TC ay0 = st[cy][ty + 1][tx + 1], ay1 = st[cy][ty + 1][tx], ay2 = st[cy][ty][tx + 1], ay3 = st[cy][ty][tx];
+        const TC az0 = st[cz][ty + 1][tx + 1], az1 = st[cz][ty + 1][tx], az2 = st[cz][ty][tx + 1], az3 = st[cz][ty][tx];
         Pt[j] = TC(0.25) * (((ax1 + ax3) - (ax0 + ax2)) + ((ay2 + ay3) - (ay0 + ay1)));
         Qt[j] = TC(0.25) * ((az0 + az1) + (az2 + az3));
-        const TC bx0 = ss[ty + 1][tx + 1][cx], bx1 = ss[ty + 1][tx][cx], bx2 = ss[ty][tx + 1][cx], bx3 = ss[ty][tx][cx];
-        const TC by0 = ss[ty + 1][tx + 1][cy], by1 = ss[ty + 1][tx][cy], by2 = ss[ty][tx + 1][cy], by3 = ss[ty][tx][cy];
-        const TC bz0 = ss[ty + 1][tx + 1][cz], bz1 = ss[ty + 1][tx][cz], bz2 = ss[ty][tx + 1][cz], bz3 = ss[ty][tx][cz];
+        const TC bx0 = ss[cx][ty + 1][tx + 1], bx1 = ss[cx][ty + 1][tx], bx2 = ss[cx][ty][tx + 1], bx3 = ss[cx][ty][tx];
+        const TC by0 = ss[cy][ty + 1][tx + 1], by1 = ss[cy][ty + 1][tx], by2 = ss[cy][ty][tx + 1], by3 = ss[cy][ty][tx];
+        const TC bz0 = ss[cz][ty + 1][tx + 1], bz1 = ss[cz][ty + 1][tx], bz2 = ss[cz][ty][tx + 1], bz3 = ss[cz][ty][tx];
         Ps[j] = TC(0.25) * (((bx1 + bx3) - (bx0 + bx2)) + ((by2 + by3) - (by0 + by1)));
         Qs[j] = TC(0.25) * ((bz0 + bz1) + (bz2 + bz3));
       } else {
-        Pt[j] = (st[ty + 1][tx + 1][cx] - st[ty + 1][tx][cx]) + (st[ty + 1][tx + 1][cy] - st[ty][tx + 1][cy]);
-        Qt[j] = st[ty + 1][tx + 1][cz];
-        Ps[j] = (ss[ty + 1][tx + 1][cx] - ss[ty + 1][tx][cx]) + (ss[ty + 1][tx + 1][cy] - ss[ty][tx + 1][cy]);
-        Qs[j] = ss[ty + 1][tx + 1][cz];
+        Pt[j] = (st[cx][ty + 1][tx + 1] - st[cx][ty + 1][tx]) + (st[cy][ty + 1][tx + 1] - st[cy][ty][tx + 1]);
+        Qt[j] = st[cz][ty + 1][tx + 1];
+        Ps[j] = (ss[cx][ty + 1][tx + 1] - ss[cx][ty + 1][tx]) + (ss[cy][ty + 1][tx + 1] - ss[cy][ty][tx + 1]);
+        Qs[j] = ss[cz][ty + 1][tx + 1];
       }
     }
     if (zz >= z0 && own) {
@@ -269,7 +299,7 @@ __global__ __launch_bounds__(Tile<TC>::DX * Tile<TC>::DY) void k_div(const TS* _
       }
       acc[0] += q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) acc[1 + k] += double(ss[ty + 1][tx + 1][k]);
+      for (int k = 0; k < 6; ++k) acc[1 + k] += double(ss[k][ty + 1][tx + 1]);
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -278,7 +308,7 @@ __global__ __launch_bounds__(Tile<TC>::DX * Tile<TC>::DY) void k_div(const TS* _
       ps[j] = Ps[j];
       qs[j] = Qs[j];
     }
-    __syncthreads();
+    lds_barrier();  // st/ss are rewritten by the next plane
   }
   block_sum<7>(acc, red);
   if (threadIdx.x == 0) {
@@ -298,14 +328,6 @@ __global__ __launch_bounds__(Tile<TC>::DX * Tile<TC>::DY) void k_div(const TS* _
 //   U plane z and z+1 in LDS (corners / voxels x0-1 .. x0+DX, y0-1 .. y0+DY),
 //   eps^(k+1), tau, sigma of voxel plane z (x0-1 .. x0+DX-1, y0-1 .. y0+DY-1).
 // --------------------------------------------------------------------------
-// Workgroup barrier that orders LDS accesses only: global loads issued before
-// it stay in flight (they prefetch the next plane).
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 template <typename T, int OP, bool AS, bool RF>
 __global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const T* __restrict__ U, const T* __restrict__ eps_in,
                                                         T* __restrict__ eps_out, const uint8_t* __restrict__ phase,
