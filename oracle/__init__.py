@@ -17,6 +17,10 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
   solve (DS, AS)              homogeneous one-step, laminate closed form,
                               direct finite-difference solve on tiny grids
                               (W, R), DS == AS fixed point
+  solve_cg (R8)               ends at the accelerated scheme's solution (all
+                              four operators), laminate closed form (W, R),
+                              homogeneous start, strain energy decreasing and
+                              C0-orthogonal residuals at every step
   laminate_exact              the oracle's own iterative solve on laminates
                               (R, W any thickness; MS, C even thickness),
                               and traction/compatibility checks
@@ -32,7 +36,7 @@ No function is left unpinned.
 """
 from .homogenization import *  # noqa: F401,F403
 from .homogenization import (  # noqa: F401
-    OPERATORS, SCHEMES, Reference, SolveResult, solve, effective_stiffness,
+    OPERATORS, SCHEMES, Reference, SolveResult, solve, solve_cg, effective_stiffness,
     reference_medium, green_apply, green_tensor_at, wave_vector, special_modes,
     equilibrium_norm, forward_dft, inverse_dft, brute_force_dft,
     voigt_to_tensor, tensor_to_voigt, stiffness_tensor, lame_from_young,

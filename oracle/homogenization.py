@@ -41,6 +41,13 @@ Readings of the paper taken here:
   R6  positions are in voxel units (spacing 1).
   R7  with more than two phases, or unequal Poisson ratios, eqs. (17)/(18)
       take the smallest and largest phase bulk and shear moduli.
+  R8  the conjugate-gradient solver that §1 and §7 name as another use of
+      the modified operators is read as plain (Hestenes-Stiefel) conjugate
+      gradients on the discrete problem of eq. (19) for the strain
+      fluctuation, in the inner product <a, b> = sum_x a : C0 : b, in which
+      G'C is self-adjoint and positive on compatible zero-mean fields
+      (G'C0G' = G'); the reference medium is that of the accelerated scheme,
+      eq. (17); see ``solve_cg``.
 """
 from __future__ import annotations
 
@@ -582,6 +589,74 @@ def solve(phase, E, nu, macro_strain, op="R", scheme="DS", tol=1e-10, max_iter=1
             eps = e
         else:
             eps = eps + 2.0 * apply_phasewise(P, phase, e - eps)
+    res.iterations = k
+    res.eps = eps
+    res.sigma = sigma
+    res.mean_stress = sigma.mean(axis=(2, 3, 4))
+    res.eta = eta
+    return res
+
+
+def solve_cg(phase, E, nu, macro_strain, op="R", tol=1e-10, max_iter=1000, ref: Reference | None = None,
+             keep_iterates=False):
+    """Conjugate gradients on the discrete Lippmann-Schwinger problem (R8).
+
+    The discrete solution is the strain eps = eps_bar + e, e compatible with
+    zero mean, whose stress sigma = C:eps is equilibrated in the sense of
+    eq. (19), i.e. G'(C:eps) = 0 at every nonzero frequency.  With
+    B(x) = G' * (C:x) (a C0-orthogonal projection composed with C, hence
+    self-adjoint and positive in <a, b> = sum_x a : C0 : b on compatible
+    fields) the fluctuation solves B(e) = -B(eps_bar).  Iteration k
+    (k = 0, 1, ...):
+      sigma^k = C:eps^k; eta^k by eq. (43); stop at the first k with
+      eta^k <= tol (or k = max_iter);
+      r^0 = -B(eps_bar), p^0 = r^0;
+      alpha = <r, r> / <p, B(p)>;  e += alpha p;  r -= alpha B(p);
+      beta = <r, r>_new / <r, r>_old;  p = r + beta p.
+    eps^0 = eps_bar.  The reference medium defaults to eq. (17).
+    """
+    phase = np.asarray(phase)
+    shape = phase.shape
+    lam, mu = lame_from_young(E, nu)
+    lam = np.atleast_1d(lam)
+    mu = np.atleast_1d(mu)
+    if ref is None:
+        ref = reference_medium(lam, mu, "AS")
+    C = [stiffness_tensor(l, m) for l, m in zip(lam, mu)]
+    C0 = stiffness_tensor(ref.lam0, ref.mu0)
+    eps_bar = voigt_to_tensor(np.asarray(macro_strain, dtype=np.float64))
+
+    def B(x):
+        return np.real(inverse_dft(green_apply(op, ref, forward_dft(apply_phasewise(C, phase, x)), shape)))
+
+    def dot(a, b):
+        return float(np.sum(a * contract(C0, b)))
+
+    eps = np.broadcast_to(eps_bar[:, :, None, None, None], (3, 3) + shape).copy()
+    r = -B(eps)
+    p = r.copy()
+    rr = dot(r, r)
+    res = SolveResult(0, None, None, None, math.inf)
+    for k in range(max_iter + 1):
+        sigma = apply_phasewise(C, phase, eps)
+        eta = equilibrium_norm(op, sigma)
+        res.eta_history.append(eta)
+        res.mean_stress_history.append(sigma.mean(axis=(2, 3, 4)))
+        if keep_iterates:
+            res.iterates.append(eps.copy())
+        if not np.isfinite(eta):
+            res.converged = False
+            break
+        if eta <= tol or k == max_iter:
+            res.converged = eta <= tol
+            break
+        q = B(p)
+        alpha = rr / dot(p, q)
+        eps = eps + alpha * p
+        r = r - alpha * q
+        rr_new = dot(r, r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
     res.iterations = k
     res.eps = eps
     res.sigma = sigma
