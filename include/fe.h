@@ -60,7 +60,20 @@ typedef enum {
                            like FE_GREEN_MS (no float64 re-anchoring).       */
 } fe_discretization;
 
-typedef enum { FE_DIRECT = 0, FE_ACCELERATED = 1 } fe_scheme; /* eqs. (9), (16) */
+typedef enum {
+  FE_DIRECT = 0,              /* eq. (9)                                            */
+  FE_ACCELERATED = 1,         /* eq. (16)                                           */
+  FE_CONJUGATE_GRADIENT = 2   /* conjugate gradients on the discrete problem of
+                                 eq. (19), the use of the modified operators that
+                                 §1 and §7 name: WP and ROT only (FE_ERR_UNSUPPORTED
+                                 at plan creation otherwise), reference medium of
+                                 eq. (17) (FE_REF_PAPER), start eps_bar only
+                                 (strain_init must be NULL), no float64
+                                 re-anchoring; a float32 run recomputes the true
+                                 residual when the recursive one reaches tol and
+                                 restarts from it, and returns FE_NOT_CONVERGED
+                                 once a restart gains less than a factor 2.      */
+} fe_scheme;
 
 /* Arithmetic of the fields, FFTs and Green operator.  Reductions (eta, mean
  * stress), reference-medium constants and the verification residual are
@@ -167,6 +180,7 @@ typedef struct {
  *   macro_strain host, 6 doubles, tensor Voigt order (eq. (4): <eps> = eps_bar)
  *   tol          > 0; iteration stops at the first k with eta^k <= tol
  *   strain_init  device, 6*N of the plan precision, or NULL for eps^0 = eps_bar
+ *                (must be NULL for FE_CONJUGATE_GRADIENT: FE_ERR_UNSUPPORTED)
  *                (eq. (9)); its mean need not equal eps_bar
  *   out          result; out->strain may be NULL (the plan then keeps the
  *                iterate in its own workspace)

@@ -129,6 +129,11 @@ struct fe_plan {
   // displacement form: second iterate and divergence buffers (allocated on first use)
   void* eps_alt = nullptr;
   void* R2 = nullptr;
+  // conjugate gradients (allocated on first use): v, r, z, p, Q (3 planes
+  // each), the sigma coefficient table and the device scalars
+  void* cg = nullptr;
+  void* coef_cg = nullptr;
+  double* cgs = nullptr;
 };
 
 // Optional per-pass timing: HIP events recorded around each launch on the
@@ -220,7 +225,10 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
   }
   if (disc < FE_GREEN_MS || disc > FE_GREEN_CENTERED)
     return fail(FE_ERR_INVALID_ARG, "unknown discretization %d", (int)disc);
-  if (scheme != FE_DIRECT && scheme != FE_ACCELERATED) return fail(FE_ERR_INVALID_ARG, "unknown scheme %d", (int)scheme);
+  if (scheme != FE_DIRECT && scheme != FE_ACCELERATED && scheme != FE_CONJUGATE_GRADIENT)
+    return fail(FE_ERR_INVALID_ARG, "unknown scheme %d", (int)scheme);
+  if (scheme == FE_CONJUGATE_GRADIENT && disc != FE_GREEN_WP && disc != FE_GREEN_ROT)
+    return fail(FE_ERR_UNSUPPORTED, "conjugate gradients run on the WP and ROT operators (displacement form)");
   if (o.precision != FE_FP32 && o.precision != FE_FP64)
     return fail(FE_ERR_INVALID_ARG, "unknown precision %d", (int)o.precision);
   if (o.max_iter < 0) return fail(FE_ERR_INVALID_ARG, "max_iter must be >= 0");
@@ -306,7 +314,7 @@ extern "C" void fe_plan_destroy(fe_plan* p) {
   (void)hipSetDevice(p->device);
   void* bufs[] = {p->eps_ws, p->R,      p->S,       p->partials, p->partials2, p->red,     p->flag,   p->coef,
                   p->coef64, p->dlt,    p->rfield,  p->dsig_hi,  p->d64,       p->s64,     p->dlt_alt, p->eps_alt,
-                  p->R2};
+                  p->R2,     p->cg,     p->coef_cg, p->cgs};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_tables(p->t32);
@@ -347,7 +355,7 @@ static RefMedium reference_medium(const fe_plan_options& o, fe_scheme scheme, co
       mmax = std::fmax(mmax, mu);
     }
     double k0, m0;
-    if (scheme == FE_ACCELERATED) {  // eq. (17)
+    if (scheme != FE_DIRECT) {  // eq. (17); conjugate gradients take the same medium
       k0 = std::sqrt(kmin * kmax);
       m0 = std::sqrt(mmin * mmax);
     } else {  // eq. (18)
@@ -456,6 +464,182 @@ static fe_status verify_fp64(fe_plan* p, const TS* eps, const uint8_t* phase, do
   return FE_OK;
 }
 
+// Conjugate gradients (displacement form, WP and ROT).  The iterate is the
+// strain eps_bar + grad v of a corner displacement v; the residual r is the
+// corner divergence of sigma of that strain (the quantity eta measures); the
+// preconditioner is the reference medium's operator, inverted by the same
+// transform passes as the fixed-point schemes (z, y, x with the Green step, y,
+// z).  These are the iterates of conjugate gradients on the strain in the
+// C0-weighted inner product.  The sign of the divergence stencil cancels in
+// alpha and beta.  Every scalar stays on the device; the host reads |r|^2 and
+// the mean stress once per iteration while the next preconditioner step runs.
+// A float32 residual drifts from the true one: when the recurrence says
+// eta <= tol the true residual is recomputed, and the iteration restarts from
+// it if it is not there (stopping when a restart gains less than 2x).
+template <typename T>
+static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<PhaseCoef<T>>& cT,
+                          const PhaseCoef<T>* coef, const GreenConst<T>& g, T* eps, double tol, fe_result* out) {
+  hipStream_t s = p->stream;
+  const Dims d = p->d;
+  const long long N = d.N, n3 = 3 * N;
+  const Tables<T>& tb = tables<T>(p);
+  const WaveTables<T> wt = wave_tables<T>(p);
+  std::vector<PhaseCoef<T>> cs(cT);  // "tau" of this table is sigma: the fused launch writes div sigma
+  for (auto& c : cs) {
+    c.dlam = c.lam;
+    c.dmu = c.mu;
+  }
+  if (!p->coef_cg) HIP_TRY(dmalloc(p, &p->coef_cg, 256 * sizeof(PhaseCoef<double>)));
+  if (!p->cgs) HIP_TRY(dmalloc(p, (void**)&p->cgs, 32 * sizeof(double)));
+  if (!p->cg) HIP_TRY(dmalloc(p, &p->cg, 5 * (size_t)n3 * sizeof(T)));
+  HIP_TRY(hipMemcpyAsync(p->coef_cg, cs.data(), cs.size() * sizeof(PhaseCoef<T>), hipMemcpyHostToDevice, s));
+  const PhaseCoef<T>* csig = static_cast<const PhaseCoef<T>*>(p->coef_cg);
+  T* v = static_cast<T*>(p->cg);
+  T* r = v + n3;
+  T* z = r + n3;
+  T* pd = z + n3;
+  T* Q = pd + n3;
+  cpx<T>* S = static_cast<cpx<T>*>(p->S);
+  double* cgs = p->cgs;
+  GreenConst<T> g0 = g;  // grad p alone: no applied strain
+  for (int i = 0; i < 6; ++i) g0.macro[i] = T(0);
+  HIP_TRY(hipMemsetAsync(v, 0, (size_t)n3 * sizeof(T), s));
+  HIP_TRY(hipMemsetAsync(cgs, 0, 32 * sizeof(double), s));
+
+  // D = div sigma(eps_bar + grad v) with |D|^2 and the sums of sigma into
+  // cgs[3], cgs[10..15] (eps_out nullable: receives the strain)
+  auto true_residual = [&](T* eps_out, T* D) {
+    const int nb = Launch<T>::update_div(v, v, eps_out, phase, csig, g, nullptr, D, nullptr, p->partials, d, p->op, 0, s);
+    launch_reduce(p->partials, nb, 7, cgs + 16, s);
+    launch_cg_restart(cgs, s);
+  };
+  auto precond = [&]() {  // z = K0^-1 r (up to sign) and rho = r.z
+    Launch<T>::zr2c(r, S, 3, d, tb.tw[2], s);
+    Launch<T>::yfft(S, 3, d, tb.tw[1], 0, s);
+    Launch<T>::xgreen3(S, d, tb.tw[0], wt, g, p->op, s);
+    Launch<T>::yfft(S, 3, d, tb.tw[1], 1, s);
+    Launch<T>::zc2r(S, z, 3, d, tb.tw[2], s);
+    const int nb = Launch<T>::dot(r, z, n3, p->partials, s);
+    launch_reduce(p->partials, nb, 1, cgs + 0, s);
+  };
+  // eta from |r|^2 and the voxel sums of sigma (host copy of cgs[3], cgs[10..15])
+  double mean[6] = {0, 0, 0, 0, 0, 0};
+  auto eta_of = [&]() {
+    for (int i = 0; i < 6; ++i) mean[i] = p->h_red[1 + i] / (double)N;
+    return std::sqrt(p->h_red[0] / (double)N) / frob(mean);
+  };
+  auto fetch = [&]() -> fe_status {
+    HIP_TRY(hipMemcpyAsync(p->h_red, cgs + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p->h_red + 1, cgs + 10, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    return FE_OK;
+  };
+
+  HIP_TRY(hipEventRecord(p->ev0, s));
+  true_residual(nullptr, r);
+  {
+    fe_status fs = fetch();
+    if (fs != FE_OK) return fs;
+  }
+  HIP_TRY(hipEventRecord(p->evc, s));
+  precond();
+  Launch<T>::cg_dir(pd, z, n3, cgs, 1, s);
+  HIP_TRY(hipEventSynchronize(p->evc));
+  const int max_iter = p->opt.max_iter;
+  fe_status status = FE_NOT_CONVERGED;
+  double eta = eta_of(), restart_eta = INFINITY, best = INFINITY;
+  int k = 0, best_k = 0;
+  for (;; ++k) {
+    if (out->eta_history && k < out->history_capacity) out->eta_history[k] = eta;
+    if (!std::isfinite(eta)) {
+      status = FE_DIVERGED;
+      break;
+    }
+    // The recursive residual says converged, or has not gained 5% in 20
+    // iterations: compare with the true residual.  A gap of more than 10%
+    // is rounding drift (float32 storage): restart from the true residual,
+    // unless the last restart gained less than a factor 2 (storage floor).
+    bool stalled = false;
+    if (eta < 0.95 * best) {
+      best = eta;
+      best_k = k;
+    } else if (k - best_k >= 20) {
+      stalled = true;
+    }
+    if (eta <= tol || stalled) {
+      const double eta_rec = eta;
+      true_residual(nullptr, Q);  // Q is free until the next step
+      fe_status fs = fetch();
+      if (fs != FE_OK) return fs;
+      HIP_TRY(hipStreamSynchronize(s));
+      eta = eta_of();
+      if (out->eta_history && k < out->history_capacity) out->eta_history[k] = eta;
+      if (eta <= tol) {
+        status = FE_OK;
+        break;
+      }
+      best = std::fmin(best, eta);
+      best_k = k;
+      if (std::fabs(eta - eta_rec) > 0.1 * eta_rec) {
+        if (!(eta < 0.5 * restart_eta)) break;  // storage floor: a restart no longer gains
+        restart_eta = eta;
+        best = eta;
+        true_residual(nullptr, r);
+        precond();
+        Launch<T>::cg_dir(pd, z, n3, cgs, 1, s);
+      }
+    }
+    if (k >= max_iter) break;
+    // Q = div sigma(grad p) = -K p (up to the stencil's sign), its sums of sigma, and p.Q
+    int nb = Launch<T>::update_div(pd, pd, nullptr, phase, csig, g0, nullptr, Q, nullptr, p->partials, d, p->op, 0, s);
+    launch_reduce(p->partials, nb, 7, cgs + 16, s);
+    nb = Launch<T>::dot(pd, Q, n3, p->partials, s);
+    launch_reduce(p->partials, nb, 1, cgs + 2, s);
+    nb = Launch<T>::cg_step(v, pd, r, Q, n3, cgs, p->partials, s);
+    launch_reduce(p->partials, nb, 1, cgs + 3, s);
+    fe_status fs = fetch();
+    if (fs != FE_OK) return fs;
+    HIP_TRY(hipEventRecord(p->evc, s));
+    precond();  // queued while the host reads eta^(k+1)
+    Launch<T>::cg_dir(pd, z, n3, cgs, 0, s);
+    HIP_TRY(hipEventSynchronize(p->evc));
+    eta = eta_of();
+    HIP_TRY(hipGetLastError());
+  }
+  // the strain eps_bar + grad v, its residual and mean stress
+  true_residual(eps, r);
+  {
+    fe_status fs = fetch();
+    if (fs != FE_OK) return fs;
+  }
+  HIP_TRY(hipEventRecord(p->ev1, s));
+  HIP_TRY(hipEventSynchronize(p->ev1));
+  const double eta_end = eta_of();
+  float ms_elapsed = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms_elapsed, p->ev0, p->ev1));
+  for (int i = 0; i < 8; ++i) {
+    out->pass_seconds[i] = 0.0;
+    out->pass_launches[i] = 0;
+  }
+  out->refinements = 0;
+  if (out->stress) Launch<T>::stress(eps, phase, coef, static_cast<T*>(out->stress), N, s);
+  double ev = eta_end;
+  if (sizeof(T) == 4) {
+    fe_status vs = verify_fp64<T>(p, eps, phase, &ev);
+    if (vs != FE_OK) return vs;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  out->iterations = k;
+  out->eta = status == FE_OK ? eta : eta_end;
+  out->eta_verify_fp64 = ev;
+  out->seconds = ms_elapsed * 1e-3;
+  for (int i = 0; i < 6; ++i) out->mean_stress[i] = mean[i];
+  if (status == FE_NOT_CONVERGED)
+    fail(status, "not converged after %d iterations (eta = %.3e, tol = %.3e)", k, eta_end, tol);
+  else if (status == FE_DIVERGED)
+    fail(status, "diverged at iteration %d (eta = %.3e)", k, eta);
+  return status;
+}
+
 template <typename T>
 static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials& mat, const double* macro, double tol,
                             const void* strain_init, fe_result* out) {
@@ -504,6 +688,7 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     if (!p->eps_ws) HIP_TRY(dmalloc(p, &p->eps_ws, 6 * (size_t)N * sizeof(T)));
     eps = static_cast<T*>(p->eps_ws);
   }
+  if (p->scheme == FE_CONJUGATE_GRADIENT) return solve_cg<T>(p, phase, cT, coef, g, eps, tol, out);
   if (strain_init) {
     if (strain_init != eps)
       HIP_TRY(hipMemcpyAsync(eps, strain_init, 6 * (size_t)N * sizeof(T), hipMemcpyDeviceToDevice, s));
@@ -734,6 +919,11 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       const int nh = (int)hist.size();
       if (can_refine && !need_anchor && k - last_anchor >= anchor_gap && nh > W && eta > 0.7 * hist[nh - 1 - W])
         need_anchor = true;
+      // the float32 floor after fast convergence: the last 2 checks gained less
+      // than 30% where the 5 before fell by at least 0.8x per check
+      if (can_refine && !need_anchor && k - last_anchor >= 8 && nh >= 8 && eta > 0.7 * hist[nh - 3] &&
+          hist[nh - 3] < std::pow(0.8, 5) * hist[nh - 8])
+        need_anchor = true;
       // float32 without re-anchoring: stop at the storage floor (no 5% gain in 100 iterations)
       if (!can_refine && sizeof(T) == 4) {
         if (eta < 0.95 * best) {
@@ -821,6 +1011,8 @@ extern "C" fe_status fe_solve(fe_plan* p, const uint8_t* phase, fe_materials mat
     return fail(FE_ERR_INVALID_ARG, "eta_history is NULL with a positive capacity");
   fe_status st = validate_materials(materials);
   if (st != FE_OK) return st;
+  if (p->scheme == FE_CONJUGATE_GRADIENT && strain_init)
+    return fail(FE_ERR_UNSUPPORTED, "conjugate gradients start from the applied strain (strain_init must be NULL)");
   HIP_TRY(hipSetDevice(p->device));
   if (p->opt.precision == FE_FP64)
     return solve_impl<double>(p, phase, materials, macro_strain, tol, strain_init, out);
@@ -1158,6 +1350,8 @@ extern "C" fe_status fe_solve_batched(fe_discretization disc, fe_scheme scheme, 
   if (disc != FE_GREEN_WP && disc != FE_GREEN_ROT)
     return fail(disc == FE_GREEN_MS || disc == FE_GREEN_CENTERED ? FE_ERR_UNSUPPORTED : FE_ERR_INVALID_ARG,
                 "batched solves support the WP and ROT operators");
+  if (scheme == FE_CONJUGATE_GRADIENT)
+    return fail(FE_ERR_UNSUPPORTED, "batched solves run the direct and accelerated schemes");
   if (scheme != FE_DIRECT && scheme != FE_ACCELERATED) return fail(FE_ERR_INVALID_ARG, "unknown scheme");
   fe_plan_options o;
   fe_plan_options_default(&o);

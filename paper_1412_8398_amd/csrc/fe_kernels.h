@@ -105,7 +105,7 @@ struct Launch {
   static int div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, const T* Dsig_base,
                  double* partials, Dims d, int op, hipStream_t s, Batch bt = Batch{nullptr, 0}, int nsamp = 1);
   // Strain update then div in one walk: eps_out = update(U, eps_in) and D =
-  // div tau(eps_out) with eta's partial sums; eps_in and eps_out must not
+  // div tau(eps_out) with eta's partial sums (eps_out nullable: not written); eps_in and eps_out must not
   // overlap.  rfield (nullable, 6 planes) replaces the constant applied
   // strain; gs (nullable) holds per-sample constants that replace g.  Returns
   // the number of partial sums (same tiling as div).
@@ -114,6 +114,11 @@ struct Launch {
                         int op, int accelerated, hipStream_t s, Batch bt = Batch{nullptr, 0},
                         const GreenConst<T>* gs = nullptr, int nsamp = 1);
   static void axpy(T* y, const T* x, long long n, hipStream_t s);  // y += x
+  // Conjugate gradients (displacement form; scalars in cgs, see k_cg_step).
+  // dot and cg_step return the number of partial sums (one double each).
+  static int dot(const T* a, const T* b, long long n, double* partials, hipStream_t s);
+  static int cg_step(T* v, const T* p, T* r, const T* Q, long long n, double* cgs, double* partials, hipStream_t s);
+  static void cg_dir(T* p, const T* z, long long n, const double* cgs, int first, hipStream_t s);
   static void xgreen3(cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> wt, GreenConst<T> g, int op,
                       hipStream_t s, Batch bt = Batch{nullptr, 0}, const GreenConst<T>* gs = nullptr, int nsamp = 1);
 
@@ -139,6 +144,10 @@ struct Launch {
   static void stress(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* sigma, long long N,
                      hipStream_t s);
 };
+
+// Conjugate gradients: |r|^2 and the sums of sigma taken from the last fused
+// gradient/divergence launch's reduced sums (cgs[16..22]).
+void launch_cg_restart(double* cgs, hipStream_t s);
 
 // float64 verification of eta from a strain of storage type TS (ROT, WP).
 // Returns the number of partial sums (7 doubles each) written.

@@ -342,7 +342,7 @@ __global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const 
     const long long smp = bt.active ? bt.active[blockIdx.y] : 0;
     U += smp * 3 * N;
     eps_in += smp * 6 * N;
-    eps_out += smp * 6 * N;
+    if (eps_out) eps_out += smp * 6 * N;
     phase += smp * N;
     coef += smp * bt.ncoef;
     if (RF) rfield += smp * 6 * N;
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const 
       const PhaseCoef<T> pc = sc[preg[q]];
       T e[6];
       strain_update<T, AS>(gr, base, ereg[q], pc, e);
-      if (i >= 1 && j >= 1 && xg < nx && yg < ny && zz >= z0)
+      if (eps_out && i >= 1 && j >= 1 && xg < nx && yg < ny && zz >= z0)
 #pragma unroll
         for (int k = 0; k < 6; ++k) eps_out[k * N + v] = e[k];
       T t[6], sg[6];
@@ -632,6 +632,72 @@ template <typename T>
 __global__ void k_axpy(T* __restrict__ y, const T* __restrict__ x, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     y[i] += x[i];
+}
+
+// --------------------------------------------------------------------------
+// Conjugate gradients on the corner displacement (displacement form).  The
+// scalars live on the device (cgs, doubles), so no iteration waits for the
+// host: 0 rho = r.z, 1 the previous rho, 2 p.Q with Q = div sigma(grad p)
+// (= -K p), 3 |r|^2 summed over corners, 10..15 the voxel sums of sigma of
+// the current iterate, 16..22 the seven reduced sums of the last fused
+// gradient/divergence launch (|div sigma|^2, then the six sums of sigma).
+// --------------------------------------------------------------------------
+constexpr int kCgBlocks = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dot3(const T* __restrict__ a, const T* __restrict__ b, long long n,
+                                              double* __restrict__ partials) {
+  __shared__ double red[16];
+  double acc[1] = {0.0};
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    acc[0] += double(a[i]) * double(b[i]);
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+}
+
+// alpha = rho / (p.K p) = rho / (-p.Q); v += alpha p; r -= alpha K p = r + alpha Q;
+// partial sums of |r|^2.  Block 0 also moves rho to the previous-rho slot and
+// adds alpha times the sums of sigma(grad p) to those of the iterate (no
+// other block touches those slots).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ v, const T* __restrict__ p, T* __restrict__ r,
+                                                 const T* __restrict__ Q, long long n, double* __restrict__ cgs,
+                                                 double* __restrict__ partials) {
+  __shared__ double red[16];
+  const double alpha = cgs[0] / -cgs[2];
+  const T a = T(alpha);
+  double acc[1] = {0.0};
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    v[i] += a * p[i];
+    const T ri = r[i] + a * Q[i];
+    r[i] = ri;
+    acc[0] += double(ri) * double(ri);
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = acc[0];
+    if (blockIdx.x == 0) {
+      cgs[1] = cgs[0];
+      for (int k = 0; k < 6; ++k) cgs[10 + k] += alpha * cgs[17 + k];
+    }
+  }
+}
+
+// p = z + beta p, beta = rho / previous rho (p = z when first)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_dir(T* __restrict__ p, const T* __restrict__ z, long long n,
+                                                const double* __restrict__ cgs, int first) {
+  const T beta = first ? T(0) : T(cgs[0] / cgs[1]);
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    p[i] = first ? z[i] : z[i] + beta * p[i];
+}
+
+// restart: |r|^2 and the sums of sigma from the last fused launch's sums
+__global__ void k_cg_restart(double* __restrict__ cgs) {
+  if (threadIdx.x == 0) {
+    cgs[3] = cgs[16];
+    for (int k = 0; k < 6; ++k) cgs[10 + k] = cgs[17 + k];
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -834,6 +900,26 @@ void Launch<T>::axpy(T* y, const T* x, long long n, hipStream_t s) {
 }
 
 template <typename T>
+int Launch<T>::dot(const T* a, const T* b, long long n, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL((k_dot3<T>), dim3(kCgBlocks), dim3(256), 0, s, a, b, n, partials);
+  return kCgBlocks;
+}
+
+template <typename T>
+int Launch<T>::cg_step(T* v, const T* p, T* r, const T* Q, long long n, double* cgs, double* partials,
+                       hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_step<T>), dim3(kCgBlocks), dim3(256), 0, s, v, p, r, Q, n, cgs, partials);
+  return kCgBlocks;
+}
+
+template <typename T>
+void Launch<T>::cg_dir(T* p, const T* z, long long n, const double* cgs, int first, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_dir<T>), dim3(kCgBlocks), dim3(256), 0, s, p, z, n, cgs, first);
+}
+
+void launch_cg_restart(double* cgs, hipStream_t s) { hipLaunchKernelGGL(k_cg_restart, dim3(1), dim3(64), 0, s, cgs); }
+
+template <typename T>
 void Launch<T>::tau6(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* out, int write_sigma,
                      double* partials, int nblocks, Dims d, hipStream_t s) {
   hipLaunchKernelGGL((k_tau6<T>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef, out, write_sigma, partials,
@@ -869,6 +955,9 @@ void launch_reduce(const double* partials, int nblocks, int nv, double* out, hip
   template int Launch<T>::div(const T*, const uint8_t*, const PhaseCoef<T>*, T*, const T*, double*, Dims, int, \
                               hipStream_t, Batch, int);                                                   \
   template void Launch<T>::axpy(T*, const T*, long long, hipStream_t);                                     \
+  template int Launch<T>::dot(const T*, const T*, long long, double*, hipStream_t);                        \
+  template int Launch<T>::cg_step(T*, const T*, T*, const T*, long long, double*, double*, hipStream_t);    \
+  template void Launch<T>::cg_dir(T*, const T*, long long, const double*, int, hipStream_t);               \
   template int Launch<T>::update_div(const T*, const T*, T*, const uint8_t*, const PhaseCoef<T>*, GreenConst<T>, \
                                      const T*, T*, const T*, double*, Dims, int, int, hipStream_t, Batch,         \
                                      const GreenConst<T>*, int);                                                  \
