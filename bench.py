@@ -90,17 +90,24 @@ def measured_traffic(pass_name: str, L: int):
 def time_to_tolerance(fe, torch, np, phase, E, nu, L, weights):
     """Time to eta <= 1e-6 from the plain start (eps^0 = eps_bar) and from the
     learned warm start (network prediction, its time included), same plan,
-    same tolerance; float64 re-anchoring as the plan's default."""
+    same tolerance; float64 re-anchoring as the plan's default.  The plan's
+    first solve allocates the re-anchoring workspace: it is timed separately
+    (first_call_seconds) and the reported times are those of a warm plan."""
     tol = 1e-6
     eps = torch.empty((6, L, L, L), dtype=torch.float32, device="cuda")
     out = {"tol": tol}
     with fe.Plan(L, green="R", scheme="AS", precision="fp32", max_iter=2000) as plan:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        plan.solve(phase, E, nu, MACRO, tol, strain=eps, history=1)
+        torch.cuda.synchronize()
+        t_first = time.perf_counter() - t0
+        t0 = time.perf_counter()
         r = plan.solve(phase, E, nu, MACRO, tol, strain=eps, history=1)
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
-        out["plain"] = {"seconds": round(t_plain, 4), "iterations": r.iterations, "status": r.status,
+        out["plain"] = {"seconds": round(t_plain, 4), "first_call_seconds": round(t_first, 4),
+                        "iterations": r.iterations, "status": r.status,
                         "eta0": float(r.eta_history[0]), "eta": r.eta, "eta_verify_fp64": r.eta_verify_fp64,
                         "refinements": r.refinements, "C_12_12": float(r.mean_stress[5]) / 2.0}
         out["learned"] = None

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(Tile<TC>::DX * Tile<TC>::DY) void k_div(const TS* _
 //   U plane z and z+1 in LDS (corners / voxels x0-1 .. x0+DX, y0-1 .. y0+DY),
 //   eps^(k+1), tau, sigma of voxel plane z (x0-1 .. x0+DX-1, y0-1 .. y0+DY-1).
 // --------------------------------------------------------------------------
-template <typename T, int OP, bool AS, bool RF>
+template <typename T, int OP, bool AS, bool RF, bool WE>
 __global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const T* __restrict__ U, const T* __restrict__ eps_in,
                                                         T* __restrict__ eps_out, const uint8_t* __restrict__ phase,
                                                         const PhaseCoef<T>* __restrict__ coef, int ncoef,
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const 
     const long long smp = bt.active ? bt.active[blockIdx.y] : 0;
     U += smp * 3 * N;
     eps_in += smp * 6 * N;
-    if (eps_out) eps_out += smp * 6 * N;
+    if (WE) eps_out += smp * 6 * N;
     phase += smp * N;
     coef += smp * bt.ncoef;
     if (RF) rfield += smp * 6 * N;
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const 
       const PhaseCoef<T> pc = sc[preg[q]];
       T e[6];
       strain_update<T, AS>(gr, base, ereg[q], pc, e);
-      if (eps_out && i >= 1 && j >= 1 && xg < nx && yg < ny && zz >= z0)
+      if (WE && i >= 1 && j >= 1 && xg < nx && yg < ny && zz >= z0)
 #pragma unroll
         for (int k = 0; k < 6; ++k) eps_out[k * N + v] = e[k];
       T t[6], sg[6];
@@ -843,11 +843,14 @@ int Launch<T>::update_div(const T* U, const T* eps_in, T* eps_out, const uint8_t
 #define FE_UD(OPV, ASV)                                                                                          \
   do {                                                                                                             \
     if (rfield)                                                                                                    \
-      hipLaunchKernelGGL((k_update_div<T, OPV, ASV, true>), grid, block, 0, s, U, eps_in, eps_out, phase, coef,    \
-                         ncoef, g, rfield, D, Dsig_base, partials, d, gd.zchunk, bt, gs);                          \
+      hipLaunchKernelGGL((k_update_div<T, OPV, ASV, true, true>), grid, block, 0, s, U, eps_in, eps_out, phase,    \
+                         coef, ncoef, g, rfield, D, Dsig_base, partials, d, gd.zchunk, bt, gs);                    \
+    else if (eps_out)                                                                                              \
+      hipLaunchKernelGGL((k_update_div<T, OPV, ASV, false, true>), grid, block, 0, s, U, eps_in, eps_out, phase,   \
+                         coef, ncoef, g, rfield, D, Dsig_base, partials, d, gd.zchunk, bt, gs);                    \
     else                                                                                                           \
-      hipLaunchKernelGGL((k_update_div<T, OPV, ASV, false>), grid, block, 0, s, U, eps_in, eps_out, phase, coef,   \
-                         ncoef, g, rfield, D, Dsig_base, partials, d, gd.zchunk, bt, gs);                          \
+      hipLaunchKernelGGL((k_update_div<T, OPV, ASV, false, false>), grid, block, 0, s, U, eps_in, eps_out, phase,  \
+                         coef, ncoef, g, rfield, D, Dsig_base, partials, d, gd.zchunk, bt, gs);                    \
   } while (0)
   if (op == OP_ROT) {
     if (accelerated)
