@@ -9,6 +9,7 @@ phases, macroscopic shear eps_12 = 1, float64 fields, tol 1e-8.
 
     python -m paper_1412_8398_amd.refscan --mode scan --chi 1e-5
     python -m paper_1412_8398_amd.refscan --mode descent --out d.json
+    python -m paper_1412_8398_amd.refscan --mode scan --scheme CG --chi 10
 
 Descent (§6.1): start from E0 = 0.51 (E1 + E2) for the direct scheme and
 E0 = sqrt(E1 E2) for the accelerated one; at each step compare N(E0) with
@@ -120,6 +121,8 @@ def main(argv=None):
     ap.add_argument("--L", type=int, default=64)
     ap.add_argument("--seed", type=int, default=1412)
     ap.add_argument("--chi", type=float, default=1e-5, help="contrast of the scan")
+    ap.add_argument("--scheme", choices=("AS", "DS", "CG"), default="AS",
+                    help="scheme of the scan (CG: conjugate gradients, WP and rotated operators)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--cap", type=int, default=3000)
     ap.add_argument("--out", default=None)
@@ -137,17 +140,20 @@ def main(argv=None):
         grid = [0.005, 0.01, 0.02, 0.03, 0.04, 0.05, 0.06, 0.07, 0.08, 0.09, 0.1, 0.12, 0.14, 0.17, 0.2, 0.25,
                 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0]
         scan = {}
-        for op in OPS:
-            cnt = Counter(phase, args.chi, op, "AS", args.tol, args.cap)
+        ops = ("W", "R") if args.scheme == "CG" else OPS
+        for op in ops:
+            cnt = Counter(phase, args.chi, op, args.scheme, args.tol, args.cap)
             scan[op] = []
             for E0 in grid:
                 n, eta = cnt(E0)
                 scan[op].append([E0, n, eta])
             best = min(scan[op], key=lambda r: (r[1], r[2]))
-            print(json.dumps({"msg": "scan", "op": op, "chi": args.chi, "best_E0": best[0], "best_N": best[1],
+            print(json.dumps({"msg": "scan", "op": op, "scheme": args.scheme, "chi": args.chi, "best_E0": best[0],
+                              "best_N": best[1], "N": [r[1] for r in scan[op]],
                               "seconds": round(time.time() - t0, 1)}), flush=True)
-        out["scan"] = {"chi": args.chi, "scheme": "AS", "E0": grid, "N": {op: [r[1] for r in scan[op]] for op in OPS},
-                       "eta": {op: [r[2] for r in scan[op]] for op in OPS}}
+        out["scan"] = {"chi": args.chi, "scheme": args.scheme, "E0": grid,
+                       "N": {op: [r[1] for r in scan[op]] for op in ops},
+                       "eta": {op: [r[2] for r in scan[op]] for op in ops}}
     if args.mode in ("descent", "both"):
         cases = [("AS", chi) for chi in (1e-5, 1e-3, 1e-1, 1e1, 1e3, 1e5)] + [("DS", chi) for chi in (1e-2, 1e2)]
         rows = []

@@ -102,3 +102,26 @@ def test_cg_error_paths():
     with pytest.raises(fe.FeError) as ei:
         fe.solve_batched([fe.BatchSampleSpec(_dev(phase), E, nu, MACRO)], 1e-6, green="R", scheme="CG")
     assert ei.value.status == fe.FE_ERR_UNSUPPORTED
+
+
+def test_cg_iteration_count_does_not_depend_on_the_reference_scale():
+    """Scaling C0 scales the preconditioner and the inner product together:
+    the conjugate-gradient iterates, hence N(E0) at fixed nu0, do not depend
+    on E0 (unlike the fixed-point schemes of §6.1); the count equals the
+    oracle's.  Porous Boolean medium, contrast 1e-3, tol 1e-8, float64."""
+    from microstructure import boolean_spheres
+
+    phase, _ = boolean_spheres((16, 16, 16), 2.5, 0.17, 1412)
+    E, nu = [1.5, 1.5e-3], [0.25, 0.25]
+    macro = [0.0, 0.0, 0.0, 0.0, 0.0, 1.0]
+    counts = []
+    for E0 in (0.05, 0.5, 5.0):
+        with fe.Plan(16, green="R", scheme="CG", precision="fp64", max_iter=3000, ref_rule="explicit", E0=E0,
+                     nu0=0.25) as plan:
+            r = plan.solve(_dev(phase), E, nu, macro, 1e-8, raise_on_error=False)
+        assert r.status == fe.FE_OK
+        counts.append(r.iterations)
+    ref = O.solve_cg(phase, E, nu, macro, op="R", tol=1e-8, max_iter=3000,
+                     ref=O.reference_medium(None, None, "AS", E0=0.5, nu0=0.25))
+    print(counts, ref.iterations, flush=True)
+    assert counts[0] == counts[1] == counts[2] == ref.iterations
