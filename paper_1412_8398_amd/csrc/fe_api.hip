@@ -782,6 +782,8 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     return FE_OK;
   };
   // float64 eta of the strain eps (+ it if anchored), folding it into eps
+  // (folded: the correction is zero and eps holds the strain that was verified)
+  bool folded = false;
   auto verify_total = [&](double* ev) -> fe_status {
     fe_status ss = sync_iterate();
     if (ss != FE_OK) return ss;
@@ -789,6 +791,7 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       Launch<T>::axpy(eps, it, 6 * N, s);
       HIP_TRY(hipMemsetAsync(it, 0, 6 * (size_t)N * sizeof(T), s));
     }
+    folded = true;
     return verify_fp64<T>(p, eps, phase, ev);
   };
 
@@ -959,7 +962,8 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     }
     HIP_TRY(hipGetLastError());
   }
-  if (anchored) {  // the returned strain is anchor + correction
+  const bool verified_final = folded && status == FE_OK;  // eps is the strain just verified
+  if (anchored && !verified_final) {  // the returned strain is anchor + correction
     Launch<T>::axpy(eps, it, 6 * N, s);
     HIP_TRY(hipMemsetAsync(it, 0, 6 * (size_t)N * sizeof(T), s));
   } else {
@@ -981,8 +985,12 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
   if (out->stress) Launch<T>::stress(eps, phase, coef, static_cast<T*>(out->stress), N, s);
   double ev = eta;
   if (sizeof(T) == 4) {
-    fe_status vs = verify_fp64<T>(p, eps, phase, &ev);
-    if (vs != FE_OK) return vs;
+    if (verified_final) {
+      ev = verified;
+    } else {
+      fe_status vs = verify_fp64<T>(p, eps, phase, &ev);
+      if (vs != FE_OK) return vs;
+    }
   }
   HIP_TRY(hipStreamSynchronize(s));
   out->iterations = k;
