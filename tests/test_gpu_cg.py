@@ -125,3 +125,22 @@ def test_cg_iteration_count_does_not_depend_on_the_reference_scale():
                      ref=O.reference_medium(None, None, "AS", E0=0.5, nu0=0.25))
     print(counts, ref.iterations, flush=True)
     assert counts[0] == counts[1] == counts[2] == ref.iterations
+
+
+def test_cg_one_plane_cell_and_effective_stiffness():
+    """A one-plane (2D, plane strain) cell: float64 iterates equal to the
+    oracle's; the effective stiffness from six conjugate-gradient solves
+    equals the accelerated scheme's."""
+    shape = (1, 32, 48)
+    phase, E, nu = _three_phase(shape, seed=21)
+    k = 12
+    ref = O.solve_cg(phase, E, nu, MACRO, op="R", tol=1e-300, max_iter=k)
+    res, eps = _cg(phase, E, nu, "R", "fp64", k)
+    assert res.iterations == k and _rel(eps, O.tensor_to_voigt(ref.eps)) < 1e-10
+    ph3, E3, nu3 = _three_phase((12, 16, 8), seed=4)
+    C = {}
+    for scheme in ("CG", "AS"):
+        with fe.Plan((8, 16, 12), green="W", scheme=scheme, precision="fp64", max_iter=3000) as plan:
+            C[scheme], its, st = plan.effective_stiffness(_dev(ph3), E3, nu3, 1e-11)
+        assert st == fe.FE_OK
+    assert np.allclose(C["CG"], C["AS"], rtol=1e-8, atol=1e-9)
