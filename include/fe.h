@@ -170,6 +170,11 @@ typedef struct {
   double pass_seconds[8];  /* with fe_plan_options.timing: summed device time per pass */
   int32_t pass_launches[8];/* with fe_plan_options.timing: launches per pass          */
   int32_t refinements;     /* float64 re-anchors performed (fe_plan_options.refine)   */
+  /* input (may be NULL): host, receives <sigma^k> (6 values per k, tensor Voigt
+     order, float64) for k = 0..min(n, history_capacity-1), the volume averages
+     that eta^k is normalised by; the sequence of effective-moduli estimates
+     of §6.2 */
+  double* mean_stress_history;
 } fe_result;
 
 /*

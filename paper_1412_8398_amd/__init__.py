@@ -76,6 +76,7 @@ class FeResult(C.Structure):
         ("pass_seconds", C.c_double * 8),
         ("pass_launches", C.c_int32 * 8),
         ("refinements", C.c_int32),
+        ("mean_stress_history", C.POINTER(C.c_double)),
     ]
 
 
@@ -173,6 +174,7 @@ class Result:
     mean_stress: np.ndarray
     seconds: float
     eta_history: np.ndarray = field(default=None, repr=False)
+    mean_stress_history: np.ndarray = field(default=None, repr=False)  # (k, 6)
     pass_seconds: dict = field(default=None, repr=False)
     pass_launches: dict = field(default=None, repr=False)
     refinements: int = 0
@@ -239,10 +241,11 @@ class Plan:
         self.close()
 
     def solve(self, phase, E, nu, macro_strain, tol, strain_init=None, strain=None, stress=None, history=0,
-              raise_on_error=True) -> Result:
+              raise_on_error=True, mean_history=False) -> Result:
         """fe_solve.  ``phase`` is a device uint8 tensor of the grid's shape;
         ``strain``/``stress`` optional device tensors (6, nz, ny, nx) of the
-        plan precision that receive eps^n and sigma^n."""
+        plan precision that receive eps^n and sigma^n; ``history`` entries of
+        eta^k (and of <sigma^k> with ``mean_history``)."""
         m, keep = _materials(E, nu)
         macro = (C.c_double * 6)(*[float(v) for v in macro_strain])
         r = FeResult()
@@ -253,6 +256,10 @@ class Plan:
             hist = np.zeros(int(history), dtype=np.float64)
             r.eta_history = hist.ctypes.data_as(C.POINTER(C.c_double))
             r.history_capacity = int(history)
+        mhist = None
+        if history and mean_history:
+            mhist = np.zeros((int(history), 6), dtype=np.float64)
+            r.mean_stress_history = mhist.ctypes.data_as(C.POINTER(C.c_double))
         s = self._lib.fe_solve(self._h, _ptr(phase), m, macro, float(tol), _ptr(strain_init), C.byref(r))
         if s < 0 and raise_on_error:
             raise FeError(s, "fe_solve")
@@ -263,6 +270,8 @@ class Plan:
         res.refinements = int(r.refinements)
         if hist is not None:
             res.eta_history = hist[: min(len(hist), r.iterations + 1)]
+        if mhist is not None:
+            res.mean_stress_history = mhist[: min(len(mhist), r.iterations + 1)]
         return res
 
     def effective_stiffness(self, phase, E, nu, tol):

@@ -528,6 +528,12 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
     for (int i = 0; i < 6; ++i) mean[i] = p->h_red[1 + i] / (double)N;
     return std::sqrt(p->h_red[0] / (double)N) / frob(mean);
   };
+  auto record = [&](int kk, double e) {
+    if (kk >= out->history_capacity) return;
+    if (out->eta_history) out->eta_history[kk] = e;
+    if (out->mean_stress_history)
+      for (int i = 0; i < 6; ++i) out->mean_stress_history[6 * kk + i] = mean[i];
+  };
   auto fetch = [&]() -> fe_status {
     HIP_TRY(hipMemcpyAsync(p->h_red, cgs + 3, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(p->h_red + 1, cgs + 10, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -549,7 +555,7 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
   double eta = eta_of(), restart_eta = INFINITY, best = INFINITY;
   int k = 0, best_k = 0;
   for (;; ++k) {
-    if (out->eta_history && k < out->history_capacity) out->eta_history[k] = eta;
+    record(k, eta);
     if (!std::isfinite(eta)) {
       status = FE_DIVERGED;
       break;
@@ -572,7 +578,7 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
       if (fs != FE_OK) return fs;
       HIP_TRY(hipStreamSynchronize(s));
       eta = eta_of();
-      if (out->eta_history && k < out->history_capacity) out->eta_history[k] = eta;
+      record(k, eta);
       if (eta <= tol) {
         status = FE_OK;
         break;
@@ -799,6 +805,12 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
   PassTimer tm(p, p->opt.timing != 0);
   fe_status status = FE_NOT_CONVERGED;
   double eta = NAN, prev_eta = INFINITY, mean[6] = {0, 0, 0, 0, 0, 0};
+  auto record = [&](int kk, double e) {
+    if (kk >= out->history_capacity) return;
+    if (out->eta_history) out->eta_history[kk] = e;
+    if (out->mean_stress_history)
+      for (int i = 0; i < 6; ++i) out->mean_stress_history[6 * kk + i] = mean[i];
+  };
   double verified = NAN, last_verified = INFINITY;
   const int W = 10;
   std::vector<double> hist;
@@ -874,7 +886,7 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       for (int i = 0; i < 6; ++i) mean[i] = mean_hi[i] + p->h_red[1 + i] / (double)N;
       const double nrm = frob(mean);
       eta = p->displacement ? std::sqrt(p->h_red[0] / (double)N) / nrm : std::sqrt(p->h_red[8]) / ((double)N * nrm);
-      if (out->eta_history && k < out->history_capacity) out->eta_history[k] = eta;
+      record(k, eta);
       hist.push_back(eta);
       if (!std::isfinite(eta)) {
         status = FE_DIVERGED;
@@ -1015,8 +1027,8 @@ extern "C" fe_status fe_solve(fe_plan* p, const uint8_t* phase, fe_materials mat
   for (int i = 0; i < 6; ++i)
     if (!std::isfinite(macro_strain[i])) return fail(FE_ERR_INVALID_ARG, "macro_strain[%d] is not finite", i);
   if (out->history_capacity < 0) return fail(FE_ERR_INVALID_ARG, "history_capacity < 0");
-  if (out->history_capacity > 0 && !out->eta_history)
-    return fail(FE_ERR_INVALID_ARG, "eta_history is NULL with a positive capacity");
+  if (out->history_capacity > 0 && !out->eta_history && !out->mean_stress_history)
+    return fail(FE_ERR_INVALID_ARG, "eta_history and mean_stress_history are NULL with a positive capacity");
   fe_status st = validate_materials(materials);
   if (st != FE_OK) return st;
   if (p->scheme == FE_CONJUGATE_GRADIENT && strain_init)
