@@ -507,9 +507,9 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
   HIP_TRY(hipMemsetAsync(cgs, 0, 32 * sizeof(double), s));
 
   // D = div sigma(eps_bar + grad v) with |D|^2 and the sums of sigma into
-  // cgs[3], cgs[10..15] (eps_out nullable: receives the strain)
-  auto true_residual = [&](T* eps_out, T* D) {
-    const int nb = Launch<T>::update_div(v, v, eps_out, phase, csig, g, nullptr, D, nullptr, p->partials, d, p->op, 0, s);
+  // cgs[3], cgs[10..15]; the strain goes to eps (free until the end)
+  auto true_residual = [&](T* D) {
+    const int nb = Launch<T>::update_div(v, v, eps, phase, csig, g, nullptr, D, nullptr, p->partials, d, p->op, 0, s);
     launch_reduce(p->partials, nb, 7, cgs + 16, s);
     launch_cg_restart(cgs, s);
   };
@@ -541,7 +541,7 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
   };
 
   HIP_TRY(hipEventRecord(p->ev0, s));
-  true_residual(nullptr, r);
+  true_residual(r);
   {
     fe_status fs = fetch();
     if (fs != FE_OK) return fs;
@@ -573,7 +573,7 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
     }
     if (eta <= tol || stalled) {
       const double eta_rec = eta;
-      true_residual(nullptr, Q);  // Q is free until the next step
+      true_residual(Q);  // Q is free until the next step
       fe_status fs = fetch();
       if (fs != FE_OK) return fs;
       HIP_TRY(hipStreamSynchronize(s));
@@ -589,17 +589,15 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
         if (!(eta < 0.5 * restart_eta)) break;  // storage floor: a restart no longer gains
         restart_eta = eta;
         best = eta;
-        true_residual(nullptr, r);
+        true_residual(r);
         precond();
         Launch<T>::cg_dir(pd, z, n3, cgs, 1, s);
       }
     }
     if (k >= max_iter) break;
-    // Q = div sigma(grad p) = -K p (up to the stencil's sign), its sums of sigma, and p.Q
+    // Q = div sigma(grad p) = -K p (up to the stencil's sign) with p.Q and the sums of sigma
     int nb = Launch<T>::update_div(pd, pd, nullptr, phase, csig, g0, nullptr, Q, nullptr, p->partials, d, p->op, 0, s);
     launch_reduce(p->partials, nb, 7, cgs + 16, s);
-    nb = Launch<T>::dot(pd, Q, n3, p->partials, s);
-    launch_reduce(p->partials, nb, 1, cgs + 2, s);
     nb = Launch<T>::cg_step(v, pd, r, Q, n3, cgs, p->partials, s);
     launch_reduce(p->partials, nb, 1, cgs + 3, s);
     fe_status fs = fetch();
@@ -612,7 +610,7 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
     HIP_TRY(hipGetLastError());
   }
   // the strain eps_bar + grad v, its residual and mean stress
-  true_residual(eps, r);
+  true_residual(r);
   {
     fe_status fs = fetch();
     if (fs != FE_OK) return fs;

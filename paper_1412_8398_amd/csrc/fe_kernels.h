@@ -105,7 +105,8 @@ struct Launch {
   static int div(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* D, const T* Dsig_base,
                  double* partials, Dims d, int op, hipStream_t s, Batch bt = Batch{nullptr, 0}, int nsamp = 1);
   // Strain update then div in one walk: eps_out = update(U, eps_in) and D =
-  // div tau(eps_out) with eta's partial sums (eps_out nullable: not written); eps_in and eps_out must not
+  // div tau(eps_out) with eta's partial sums (eps_out nullable: not written, and the first of the seven sums
+  // is then U.D over the owned corners instead of |div sigma|^2); eps_in and eps_out must not
   // overlap.  rfield (nullable, 6 planes) replaces the constant applied
   // strain; gs (nullable) holds per-sample constants that replace g.  Returns
   // the number of partial sums (same tiling as div).

@@ -469,6 +469,13 @@ __global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const 
         ss[k][j][i] = sg[k];
       }
     }
+    // without the strain write (conjugate gradients) the first sum is U.D at
+    // the owned corners: read this corner's U before su[b] is refilled
+    T uc[3] = {T(0), T(0), T(0)};
+    if (!WE) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) uc[k] = su[b][k][ty + 1][tx + 1];
+    }
     if (zz + 1 < z1) fetch_e(zz + 1);  // in flight during the divergence and the next store
     lds_barrier();
     T Pt[3], Qt[3], Ps[3], Qs[3];
@@ -513,7 +520,10 @@ __global__ __launch_bounds__(Tile<T>::DX * Tile<T>::DY) void k_update_div(const 
 #pragma unroll
         for (int j = 0; j < 3; ++j) qd[j] += double(Dsig_base[j * N + c]);
       }
-      acc[0] += qd[0] * qd[0] + qd[1] * qd[1] + qd[2] * qd[2];
+      if (WE)
+        acc[0] += qd[0] * qd[0] + qd[1] * qd[1] + qd[2] * qd[2];
+      else
+        acc[0] += double(uc[0]) * double(Dt[0]) + double(uc[1]) * double(Dt[1]) + double(uc[2]) * double(Dt[2]);
 #pragma unroll
       for (int k = 0; k < 6; ++k) acc[1 + k] += double(ss[k][ty + 1][tx + 1]);
     }
@@ -637,10 +647,11 @@ __global__ void k_axpy(T* __restrict__ y, const T* __restrict__ x, long long n) 
 // --------------------------------------------------------------------------
 // Conjugate gradients on the corner displacement (displacement form).  The
 // scalars live on the device (cgs, doubles), so no iteration waits for the
-// host: 0 rho = r.z, 1 the previous rho, 2 p.Q with Q = div sigma(grad p)
-// (= -K p), 3 |r|^2 summed over corners, 10..15 the voxel sums of sigma of
-// the current iterate, 16..22 the seven reduced sums of the last fused
-// gradient/divergence launch (|div sigma|^2, then the six sums of sigma).
+// host: 0 rho = r.z, 1 the previous rho, 3 |r|^2 summed over corners,
+// 10..15 the voxel sums of sigma of the current iterate, 16..22 the seven
+// reduced sums of the last fused gradient/divergence launch: |div sigma|^2
+// (with the strain written) or p.Q with Q = div sigma(grad p) = -K p (without),
+// then the six sums of sigma.
 // --------------------------------------------------------------------------
 constexpr int kCgBlocks = 1024;
 
@@ -664,7 +675,7 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ v, const T* __r
                                                  const T* __restrict__ Q, long long n, double* __restrict__ cgs,
                                                  double* __restrict__ partials) {
   __shared__ double red[16];
-  const double alpha = cgs[0] / -cgs[2];
+  const double alpha = cgs[0] / -cgs[16];
   const T a = T(alpha);
   double acc[1] = {0.0};
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
