@@ -67,14 +67,14 @@ def optimal_E0(chi, op, cap):
     return E0, n
 
 
-def run(L, chi, op, E0, tol, cap):
+def run(L, chi, op, E0, tol, cap, scheme="AS"):
     import torch
 
     import paper_1412_8398_amd as fe
 
     ph, info = medium(L)
     phase = torch.from_numpy(ph).cuda()
-    with fe.Plan(L, green=op, scheme="AS", precision="fp64", max_iter=cap, ref_rule="explicit", E0=E0,
+    with fe.Plan(L, green=op, scheme=scheme, precision="fp64", max_iter=cap, ref_rule="explicit", E0=E0,
                  nu0=NU) as plan:
         torch.cuda.synchronize()
         t0 = time.time()
@@ -94,6 +94,8 @@ def main(argv=None):
     ap.add_argument("--ops", nargs="+", default=list(OPS))
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--cap", type=int, default=3000)
+    ap.add_argument("--scheme", choices=("AS", "CG"), default="AS",
+                    help="CG: conjugate gradients (W, R), whose iterates do not depend on E0 (taken as E1)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     rows = []
@@ -101,11 +103,15 @@ def main(argv=None):
         if name not in args.cases:
             continue
         for op in args.ops:
-            E0, n64 = optimal_E0(chi, op, 3000 if chi < 1 else 12000)
+            if args.scheme == "CG":
+                E0, n64 = E1, None
+            else:
+                E0, n64 = optimal_E0(chi, op, 3000 if chi < 1 else 12000)
             print(json.dumps({"msg": "E0", "case": name, "op": op, "E0": E0, "N64": n64}), flush=True)
-            c, r, sec, info = run(L, chi, op, E0, args.tol, args.cap)
+            c, r, sec, info = run(L, chi, op, E0, args.tol, args.cap, args.scheme)
             after = np.abs(c[10:] / c[-1] - 1.0) if len(c) > 10 else np.array([0.0])
-            row = {"case": name, "chi": chi, "L": L, "op": op, "E0": E0, "fraction": info.volume_fraction,
+            row = {"case": name, "scheme": args.scheme, "chi": chi, "L": L, "op": op, "E0": E0,
+                   "fraction": info.volume_fraction,
                    "iterations": int(r.iterations), "status": int(r.status), "eta": float(r.eta),
                    "seconds": round(sec, 2), "C1111_limit": float(c[-1]), "settle_1e-2": settle(c),
                    "max_rel_error_after_10": float(after.max()),
