@@ -937,6 +937,21 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       if (can_refine && !need_anchor && k - last_anchor >= 8 && nh >= 8 && eta > 0.7 * hist[nh - 3] &&
           hist[nh - 3] < std::pow(0.8, 5) * hist[nh - 8])
         need_anchor = true;
+      // its first sign in a steady geometric decrease: the last ratio exceeds
+      // 1.3x the mean of the 4 before, which stayed below 0.8 and within 1.3x
+      // of each other (the float32 error adds to eta in quadrature, so the
+      // ratio rises a few checks before eta stalls)
+      if (can_refine && !need_anchor && k - last_anchor >= 8 && nh >= 6 && eta < 1e-3 * hist[0]) {
+        double rmin = INFINITY, rmax = 0.0, lsum = 0.0;
+        for (int i = nh - 5; i < nh - 1; ++i) {
+          const double r = hist[i] / hist[i - 1];
+          rmin = std::fmin(rmin, r);
+          rmax = std::fmax(rmax, r);
+          lsum += std::log(r);
+        }
+        if (rmax < 0.8 && rmax < 1.3 * rmin && hist[nh - 1] > 1.3 * std::exp(0.25 * lsum) * hist[nh - 2])
+          need_anchor = true;
+      }
       // float32 without re-anchoring: stop at the storage floor (no 5% gain in 100 iterations)
       if (!can_refine && sizeof(T) == 4) {
         if (eta < 0.95 * best) {
