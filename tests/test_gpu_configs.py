@@ -71,8 +71,8 @@ def test_config2_contrast_100(boolean256):
 
 
 def test_config2_near_porous(boolean256):
-    """Slow convergence at chi = 1e-6 (the survey could not reproduce the
-    paper's porous iteration counts either): after 3000 iterations the float64
+    """Slow convergence at chi = 1e-6 (the paper's porous iteration counts
+    are not reproduced on this medium): after 3000 iterations the float64
     run is below 1e-5, the float32 run with float64 re-anchoring reaches the
     same mean stress, and the shear modulus is positive and below Voigt."""
     phase, f = boolean256
