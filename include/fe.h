@@ -68,11 +68,16 @@ typedef enum {
                                  §1 and §7 name: WP and ROT only (FE_ERR_UNSUPPORTED
                                  at plan creation otherwise), reference medium of
                                  eq. (17) (FE_REF_PAPER), start eps_bar only
-                                 (strain_init must be NULL), no float64
-                                 re-anchoring; a float32 run recomputes the true
-                                 residual when the recursive one reaches tol and
-                                 restarts from it, and returns FE_NOT_CONVERGED
-                                 once a restart gains less than a factor 2.      */
+                                 (strain_init must be NULL).  The true residual
+                                 is recomputed when the recursive one reaches
+                                 tol or stalls, and the iteration restarts from
+                                 it on drift.  Float32 plans with refine (the
+                                 default) keep the displacement in float64 and
+                                 form every true residual in float64; the
+                                 float32 strain returned must verify <= tol
+                                 (else FE_NOT_CONVERGED).  Without refine a
+                                 restart gaining less than a factor 2 ends the
+                                 run (FE_NOT_CONVERGED, float32 floor).        */
 } fe_scheme;
 
 /* Arithmetic of the fields, FFTs and Green operator.  Reductions (eta, mean

@@ -134,6 +134,10 @@ struct fe_plan {
   void* cg = nullptr;
   void* coef_cg = nullptr;
   double* cgs = nullptr;
+  // float32 conjugate gradients with float64 refinement: the displacement,
+  // the residual and a conversion buffer (3 planes each), sigma table
+  double* cg64 = nullptr;
+  void* coef_cg64 = nullptr;
 };
 
 // Optional per-pass timing: HIP events recorded around each launch on the
@@ -314,7 +318,7 @@ extern "C" void fe_plan_destroy(fe_plan* p) {
   (void)hipSetDevice(p->device);
   void* bufs[] = {p->eps_ws, p->R,      p->S,       p->partials, p->partials2, p->red,     p->flag,   p->coef,
                   p->coef64, p->dlt,    p->rfield,  p->dsig_hi,  p->d64,       p->s64,     p->dlt_alt, p->eps_alt,
-                  p->R2,     p->cg,     p->coef_cg, p->cgs};
+                  p->R2,     p->cg,     p->coef_cg, p->cgs,      p->cg64,      p->coef_cg64};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_tables(p->t32);
@@ -478,7 +482,8 @@ static fe_status verify_fp64(fe_plan* p, const TS* eps, const uint8_t* phase, do
 // it if it is not there (stopping when a restart gains less than 2x).
 template <typename T>
 static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<PhaseCoef<T>>& cT,
-                          const PhaseCoef<T>* coef, const GreenConst<T>& g, T* eps, double tol, fe_result* out) {
+                          const std::vector<PhaseCoef<double>>& c64, const PhaseCoef<T>* coef, const GreenConst<T>& g,
+                          const double* macro, T* eps, double tol, fe_result* out) {
   hipStream_t s = p->stream;
   const Dims d = p->d;
   const long long N = d.N, n3 = 3 * N;
@@ -505,10 +510,48 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
   for (int i = 0; i < 6; ++i) g0.macro[i] = T(0);
   HIP_TRY(hipMemsetAsync(v, 0, (size_t)n3 * sizeof(T), s));
   HIP_TRY(hipMemsetAsync(cgs, 0, 32 * sizeof(double), s));
+  // float32 with refinement: the displacement is v64 + v, v64 in float64;
+  // every true residual folds v into v64 and is formed in float64
+  const bool refine64 = sizeof(T) == 4 && p->opt.refine;
+  double *v64 = nullptr, *R64 = nullptr, *t64 = nullptr;
+  const PhaseCoef<double>* csig64 = nullptr;
+  GreenConst<double> g64;
+  std::memset(&g64, 0, sizeof g64);
+  if (refine64) {
+    if (!p->cg64) HIP_TRY(dmalloc(p, (void**)&p->cg64, 9 * (size_t)N * sizeof(double)));
+    if (!p->coef_cg64) HIP_TRY(dmalloc(p, &p->coef_cg64, 256 * sizeof(PhaseCoef<double>)));
+    std::vector<PhaseCoef<double>> cs64(c64);
+    for (auto& c : cs64) {
+      c.dlam = c.lam;
+      c.dmu = c.mu;
+    }
+    HIP_TRY(hipMemcpyAsync(p->coef_cg64, cs64.data(), cs64.size() * sizeof(PhaseCoef<double>),
+                           hipMemcpyHostToDevice, s));
+    csig64 = static_cast<const PhaseCoef<double>*>(p->coef_cg64);
+    v64 = p->cg64;
+    R64 = v64 + n3;
+    t64 = R64 + n3;
+    HIP_TRY(hipMemsetAsync(v64, 0, (size_t)n3 * sizeof(double), s));
+    for (int i = 0; i < 6; ++i) g64.macro[i] = macro[i];  // the strain update in float64 uses eps_bar only
+  }
 
   // D = div sigma(eps_bar + grad v) with |D|^2 and the sums of sigma into
-  // cgs[3], cgs[10..15]; the strain goes to eps (free until the end)
+  // cgs[3], cgs[10..15]; the strain goes to eps (free until the end).  With
+  // refinement: v is folded into v64 (v = 0 after) and D = float(R64).
   auto true_residual = [&](T* D) {
+    if (refine64) {
+      Launch<double>::convert_to(t64, v, 0, n3, s);
+      Launch<double>::axpy(v64, t64, n3, s);
+      (void)hipMemsetAsync(v, 0, (size_t)n3 * sizeof(T), s);
+      int nb = Launch<double>::update_div(v64, v64, nullptr, phase, csig64, g64, nullptr, R64, nullptr, p->partials,
+                                          d, p->op, 0, s);
+      launch_reduce(p->partials, nb, 7, cgs + 16, s);
+      nb = Launch<double>::dot(R64, R64, n3, p->partials, s);
+      launch_reduce(p->partials, nb, 1, cgs + 16, s);
+      launch_cg_restart(cgs, s);
+      Launch<T>::convert_to(D, R64, 1, n3, s);
+      return;
+    }
     const int nb = Launch<T>::update_div(v, v, eps, phase, csig, g, nullptr, D, nullptr, p->partials, d, p->op, 0, s);
     launch_reduce(p->partials, nb, 7, cgs + 16, s);
     launch_cg_restart(cgs, s);
@@ -615,6 +658,16 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
     fe_status fs = fetch();
     if (fs != FE_OK) return fs;
   }
+  if (refine64) {
+    // eps: the strain formed in float64 and rounded once (a float copy of the
+    // displacement would put its rounding, |v| times 6e-8, into the gradient).
+    // R64 and t64 (6 contiguous float64 planes) take the strain, r and z (3
+    // float64 planes' worth) the divergence that the launch also writes.
+    double* e64 = R64;
+    Launch<double>::update_div(v64, v64, e64, phase, csig64, g64, nullptr, reinterpret_cast<double*>(r), nullptr,
+                               p->partials, d, p->op, 0, s);
+    Launch<T>::convert_to(eps, e64, 1, 6 * N, s);
+  }
   HIP_TRY(hipEventRecord(p->ev1, s));
   HIP_TRY(hipEventSynchronize(p->ev1));
   const double eta_end = eta_of();
@@ -630,6 +683,8 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
   if (sizeof(T) == 4) {
     fe_status vs = verify_fp64<T>(p, eps, phase, &ev);
     if (vs != FE_OK) return vs;
+    // the float32 strain returned must itself meet tol (its storage floor)
+    if (status == FE_OK && refine64 && !(ev <= tol)) status = FE_NOT_CONVERGED;
   }
   HIP_TRY(hipStreamSynchronize(s));
   out->iterations = k;
@@ -692,7 +747,7 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     if (!p->eps_ws) HIP_TRY(dmalloc(p, &p->eps_ws, 6 * (size_t)N * sizeof(T)));
     eps = static_cast<T*>(p->eps_ws);
   }
-  if (p->scheme == FE_CONJUGATE_GRADIENT) return solve_cg<T>(p, phase, cT, coef, g, eps, tol, out);
+  if (p->scheme == FE_CONJUGATE_GRADIENT) return solve_cg<T>(p, phase, cT, c64, coef, g, macro, eps, tol, out);
   if (strain_init) {
     if (strain_init != eps)
       HIP_TRY(hipMemcpyAsync(eps, strain_init, 6 * (size_t)N * sizeof(T), hipMemcpyDeviceToDevice, s));

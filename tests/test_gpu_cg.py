@@ -28,10 +28,11 @@ def _three_phase(shape, seed=7):
     return ph, [1.0, 5.0, 50.0], [0.2, 0.3, 0.35]
 
 
-def _cg(phase, E, nu, op, precision, max_iter, tol=1e-300, scheme="CG"):
+def _cg(phase, E, nu, op, precision, max_iter, tol=1e-300, scheme="CG", refine=True):
     nz, ny, nx = phase.shape
     dt = torch.float64 if precision == "fp64" else torch.float32
-    with fe.Plan((nx, ny, nz), green=op, scheme=scheme, precision=precision, max_iter=max_iter) as plan:
+    with fe.Plan((nx, ny, nz), green=op, scheme=scheme, precision=precision, max_iter=max_iter,
+                 refine=refine) as plan:
         eps = torch.empty((6, nz, ny, nx), dtype=dt, device="cuda")
         res = plan.solve(_dev(phase), E, nu, MACRO, tol, strain=eps, history=max_iter + 1, raise_on_error=False)
         torch.cuda.synchronize()
@@ -74,18 +75,27 @@ def test_cg_converges_with_the_oracle_and_to_the_accelerated_solution(op):
 
 
 def test_cg_fp32_reaches_tolerance_with_fp64_verification():
-    """Float32 conjugate gradients reach 1e-5 (float64 verification agrees);
-    below the float32 storage floor of this contrast-50 cell (about 2.5e-6)
-    the run ends FE_NOT_CONVERGED with the true eta it reached."""
+    """Float32 conjugate gradients without refinement reach 1e-5 (float64
+    verification agrees) and stop at the float32 floor of this contrast-50
+    cell (about 2.5e-6) with FE_NOT_CONVERGED; with float64 refinement (the
+    default) they reach 1e-6 and 1e-7, the returned float32 strain verifying
+    to tol, and report FE_NOT_CONVERGED below what a float32 strain can hold."""
     shape = (32, 32, 32)
     phase, E, nu = _three_phase(shape, seed=5)
-    res, eps = _cg(phase, E, nu, "R", "fp32", 2000, 1e-5)
-    assert res.status == fe.FE_OK and res.eta_verify_fp64 <= 1.2e-5
     ref, _ = _cg(phase, E, nu, "R", "fp64", 2000, 1e-10)
+    res, eps = _cg(phase, E, nu, "R", "fp32", 2000, 1e-5, refine=False)
+    assert res.status == fe.FE_OK and res.eta_verify_fp64 <= 1.2e-5
     assert np.allclose(res.mean_stress, ref.mean_stress, rtol=1e-4, atol=1e-5)
-    low, _ = _cg(phase, E, nu, "R", "fp32", 2000, 1e-8)
+    low, _ = _cg(phase, E, nu, "R", "fp32", 2000, 1e-8, refine=False)
     assert low.status == fe.FE_NOT_CONVERGED and 1e-8 < low.eta_verify_fp64 < 1e-5
     assert abs(low.eta - low.eta_verify_fp64) <= 0.05 * low.eta_verify_fp64
+    for tol in (1e-6, 1e-7):
+        rr, _ = _cg(phase, E, nu, "R", "fp32", 2000, tol)
+        print(tol, rr, flush=True)
+        assert rr.status == fe.FE_OK and rr.eta <= tol and rr.eta_verify_fp64 <= tol
+        assert np.allclose(rr.mean_stress, ref.mean_stress, rtol=1e-6, atol=1e-7)
+    tiny, _ = _cg(phase, E, nu, "R", "fp32", 2000, 1e-11)
+    assert tiny.status == fe.FE_NOT_CONVERGED and tiny.eta_verify_fp64 > 1e-11
 
 
 def test_cg_error_paths():
