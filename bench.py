@@ -241,6 +241,24 @@ def main():
     step_bytes = sum(v for k, v in pb.items() if k != "pointwise")
     iter_gbs = step_bytes * K / wall / 1e9
 
+    # context for the roofline: what torch's device copy reaches on this GPU
+    # (copy_ of 2 GiB, read + write counted, best of 5; not the best possible
+    # copy, a reference point)
+    a = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    copy_gbs = 2 * a.numel() * 4 / best / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+
     tti = None
     if not args.no_tti:
         tti = time_to_tolerance(fe, torch, np, phase, E, nu, L, args.weights)
@@ -277,6 +295,9 @@ def main():
         "iteration_bytes_model": step_bytes,
         "iteration_gbs_model": round(iter_gbs, 1),
         "iteration_hbm_frac_model": round(iter_gbs / PEAK_HBM_GBS, 4),
+        "device_copy": {"gbs": round(copy_gbs, 1), "kernel": "torch copy_ of 2 GiB (read + write), best of 5",
+                         "dominant_kernel_frac": round(passes[dom]["gbs"] / copy_gbs, 4),
+                         "iteration_frac": round(iter_gbs / copy_gbs, 4)},
         "passes": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                    for k, v in passes.items()},
         "library_seconds": round(res.seconds, 4),
