@@ -37,3 +37,15 @@ def test_oracle_mirror_symmetry_of_sigma12(op, symmetric):
         assert asym < 1e-12
     else:
         assert asym > 0.1
+
+
+def test_moduli_rate_helpers():
+    """The §6.2 study's settling index and its rescaled Boolean medium (the
+    same sphere centres at every resolution)."""
+    from paper_1412_8398_amd import moduli_rate as M
+
+    assert M.settle(np.array([2.0, 1.0, 1.02, 1.001, 1.0])) == 3
+    assert M.settle(np.array([1.0, 1.0])) == 0
+    _, a = M.medium(16)
+    _, b = M.medium(32)
+    assert a.n_spheres == b.n_spheres and np.allclose(b.centers, 2 * a.centers)
