@@ -128,3 +128,37 @@ def test_batched_solve_rejects_bad_arguments_before_device_work(lib):
     nomat, keep4 = _batch_desc((16, 16, 16))
     keep4[4][0].E[0] = -1.0
     assert call(1, 0, C.byref(nomat), 1e-6) == fe.FE_ERR_INVALID_ARG
+
+
+def test_ctypes_structures_match_the_c_headers(tmp_path):
+    """Every structure the binding passes through the ABI has the C layout:
+    a C program built against include/*.h prints each size and field offset
+    (a field missing in C fails the compile)."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    import paper_1412_8398_amd as fe
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [(fe.FeGrid, "fe_grid"), (fe.FePlanOptions, "fe_plan_options"), (fe.FeMaterials, "fe_materials"),
+             (fe.FeResult, "fe_result"), (fe.FeBatchDesc, "fe_batch_desc"), (fe.FeBatchResult, "fe_batch_result"),
+             (fe.FeUnetConfig, "fe_unet_config"), (fe.FeUnetBatch, "fe_unet_batch"),
+             (fe.FeNNConvShape, "fe_nn_conv_shape")]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fe.h"', '#include "fe_nn.h"', "int main(void) {"]
+    want = []
+    for cls, cname in pairs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(cls))
+        for name, _ in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {name}));')
+            want.append(getattr(cls, name).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == want
