@@ -993,12 +993,13 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
           hist[nh - 3] < std::pow(0.8, 5) * hist[nh - 8])
         need_anchor = true;
       // its first sign in a steady geometric decrease: the last ratio exceeds
-      // 1.3x the mean of the 4 before, which stayed below 0.8 and within 1.3x
-      // of each other (the float32 error adds to eta in quadrature, so the
-      // ratio rises a few checks before eta stalls)
-      if (can_refine && !need_anchor && k - last_anchor >= 8 && nh >= 6 && eta < 1e-3 * hist[0]) {
+      // 1.3x the mean of the 4 ratios before the previous one, which stayed
+      // below 0.8 and within 1.3x of each other (the float32 error adds to
+      // eta in quadrature, so the ratio rises over a few checks before eta
+      // stalls; the previous ratio may already be rising)
+      if (can_refine && !need_anchor && k - last_anchor >= 8 && nh >= 7 && eta < 1e-3 * hist[0]) {
         double rmin = INFINITY, rmax = 0.0, lsum = 0.0;
-        for (int i = nh - 5; i < nh - 1; ++i) {
+        for (int i = nh - 6; i < nh - 2; ++i) {
           const double r = hist[i] / hist[i - 1];
           rmin = std::fmin(rmin, r);
           rmax = std::fmax(rmax, r);

@@ -59,3 +59,22 @@ def test_tolerance_below_the_float32_storage_floor_stops_early():
     assert r.status == fe.FE_NOT_CONVERGED
     assert r.iterations < 3000
     assert r.eta_verify_fp64 < 1e-6
+
+
+def test_refinement_costs_at_most_two_iterations_over_float64():
+    """The float32 floor is caught as it shows (the eta ratio rising), so the
+    refined float32 solve to 1e-6 on a 256^3 cell of the benchmark recipe
+    (spheres of radius 6, fraction 0.25, contrast 10, shear) needs at most two
+    iterations more than float64, with one or two re-anchors, and no re-anchor
+    at a tolerance above the floor."""
+    import bench
+
+    phase, _ = bench.make_phase(256)
+    E, nu, macro = list(bench.RECIPE["E"]), list(bench.RECIPE["nu"]), list(bench.MACRO)
+    r64, _ = _solve(phase, E, nu, macro, "R", "AS", "fp64", 1e-6, 500)
+    r32, _ = _solve(phase, E, nu, macro, "R", "AS", "fp32", 1e-6, 500)
+    print(r64.iterations, r32.iterations, r32.refinements, r32.eta_verify_fp64, flush=True)
+    assert r64.status == fe.FE_OK and r32.status == fe.FE_OK and r32.eta_verify_fp64 <= 1e-6
+    assert r32.iterations <= r64.iterations + 2 and 1 <= r32.refinements <= 2
+    coarse, _ = _solve(phase, E, nu, macro, "R", "AS", "fp32", 1e-4, 500)
+    assert coarse.status == fe.FE_OK and coarse.refinements == 0
