@@ -24,7 +24,6 @@ import numpy as np
 
 __all__ = [
     "SplitMix64",
-    "lame_from_young",
     "sphere_inclusion",
     "boolean_spheres",
     "sphere_array",
@@ -105,15 +104,6 @@ class SplitMix64:
     def randint(self, n: int) -> int:
         """Uniform integer in [0, n)."""
         return int(self.uniform() * n)
-
-
-def lame_from_young(E, nu):
-    """Isotropic Lame constants from Young's modulus and Poisson's ratio."""
-    E = np.asarray(E, dtype=np.float64)
-    nu = np.asarray(nu, dtype=np.float64)
-    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
-    mu = E / (2.0 * (1.0 + nu))
-    return lam, mu
 
 
 @dataclass

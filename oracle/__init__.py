@@ -13,6 +13,10 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
                               (C, W, R), symmetries eqs. (26), (27), (34),
                               projection properties, q -> 0 limit
   special_modes               eqs. (14), (29), (41) by construction + rank tests
+  reference_medium            eqs. (17), (18) through the exact error recurrence
+                              of AS and the exact error ratio of DS on a
+                              two-phase laminate (shear pins mu0, uniaxial
+                              strain pins lambda0 + 2 mu0)
   equilibrium_norm            real-space divergence stencils (Parseval)
   solve (DS, AS)              homogeneous one-step, laminate closed form,
                               direct finite-difference solve on tiny grids

@@ -144,16 +144,60 @@ class FeError(RuntimeError):
 
 
 def _ptr(x) -> int | None:
-    """Device address of a torch tensor (or an int address); None for None."""
+    """Device address of a tensor already checked by ``_checked``; None for None."""
+    return None if x is None else x.data_ptr()
+
+
+def _checked(x, name, dtypes, shape, required=False):
+    """Check a tensor handed to the library: dtype (one of ``dtypes``), exact
+    shape and contiguity.  The library takes no sizes, so a mismatch here
+    would make its kernels read or write out of bounds.  Every tensor of a
+    call is checked before any is placed (``_addresses``) and before the
+    library is called."""
     if x is None:
+        if required:
+            raise ValueError(f"{name} is required")
         return None
-    if isinstance(x, int):
-        return x
-    if not x.is_cuda:
-        raise ValueError("expected a device (cuda) tensor")
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(x).__name__}")
+    dtypes = dtypes if isinstance(dtypes, tuple) else (dtypes,)
+    if x.dtype not in dtypes:
+        raise ValueError(f"{name}: dtype {x.dtype}, expected {' or '.join(str(d) for d in dtypes)}")
+    if tuple(x.shape) != tuple(int(v) for v in shape):
+        raise ValueError(f"{name}: shape {tuple(x.shape)}, expected {tuple(shape)}")
     if not x.is_contiguous():
-        raise ValueError("expected a contiguous tensor")
-    return x.data_ptr()
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    return x
+
+
+def _addresses(named, device=None):
+    """Device addresses of checked tensors given as (name, tensor) pairs (None
+    stays None); all must live on the GPU, on ``device`` if given, else on
+    the device of the first one."""
+    out = []
+    for name, x in named:
+        if x is None:
+            out.append(None)
+            continue
+        if not x.is_cuda:
+            raise ValueError(f"{name}: expected a device (cuda) tensor")
+        if device is None:
+            device = x.device.index
+        elif x.device.index != device:
+            raise ValueError(f"{name}: on cuda:{x.device.index}, expected cuda:{device}")
+        out.append(x.data_ptr())
+    return out
+
+
+def _current_device():
+    import torch
+    return torch.cuda.current_device()
+
+
+def _field_dtype(precision):
+    import torch
+    return torch.float64 if precision == "fp64" else torch.float32
 
 
 def _materials(E, nu):
@@ -213,6 +257,7 @@ class Plan:
             raise FeError(s, "fe_plan_create")
         self._h = h
         self._lib = lib
+        self.device = _current_device()
 
     @property
     def n(self) -> int:
@@ -246,11 +291,21 @@ class Plan:
         ``strain``/``stress`` optional device tensors (6, nz, ny, nx) of the
         plan precision that receive eps^n and sigma^n; ``history`` entries of
         eta^k (and of <sigma^k> with ``mean_history``)."""
+        dt = _field_dtype(self.precision)
+        fshape = (6,) + self.shape
+        named = [("phase", _checked(phase, "phase", _uint8(), self.shape, required=True)),
+                 ("strain", _checked(strain, "strain", dt, fshape)),
+                 ("stress", _checked(stress, "stress", dt, fshape)),
+                 ("strain_init", _checked(strain_init, "strain_init", dt, fshape))]
+        mv = [float(v) for v in macro_strain]
+        if len(mv) != 6:
+            raise ValueError("macro_strain needs 6 components")
+        p_phase, p_strain, p_stress, p_init = _addresses(named, self.device)
         m, keep = _materials(E, nu)
-        macro = (C.c_double * 6)(*[float(v) for v in macro_strain])
+        macro = (C.c_double * 6)(*mv)
         r = FeResult()
-        r.strain = _ptr(strain)
-        r.stress = _ptr(stress)
+        r.strain = p_strain
+        r.stress = p_stress
         hist = None
         if history:
             hist = np.zeros(int(history), dtype=np.float64)
@@ -260,7 +315,7 @@ class Plan:
         if history and mean_history:
             mhist = np.zeros((int(history), 6), dtype=np.float64)
             r.mean_stress_history = mhist.ctypes.data_as(C.POINTER(C.c_double))
-        s = self._lib.fe_solve(self._h, _ptr(phase), m, macro, float(tol), _ptr(strain_init), C.byref(r))
+        s = self._lib.fe_solve(self._h, p_phase, m, macro, float(tol), p_init, C.byref(r))
         if s < 0 and raise_on_error:
             raise FeError(s, "fe_solve")
         del keep
@@ -276,10 +331,12 @@ class Plan:
 
     def effective_stiffness(self, phase, E, nu, tol):
         """fe_effective_stiffness: 6x6 Voigt matrix and the six iteration counts."""
+        (p_phase,) = _addresses([("phase", _checked(phase, "phase", _uint8(), self.shape, required=True))],
+                                self.device)
         m, keep = _materials(E, nu)
         Cv = (C.c_double * 36)()
         its = (C.c_int32 * 6)()
-        s = self._lib.fe_effective_stiffness(self._h, _ptr(phase), m, float(tol), Cv, its)
+        s = self._lib.fe_effective_stiffness(self._h, p_phase, m, float(tol), Cv, its)
         if s < 0:
             raise FeError(s, "fe_effective_stiffness")
         del keep
@@ -326,10 +383,21 @@ def solve_batched(samples, tol, green="R", scheme="AS", precision="fp32", max_it
     macro = (C.c_double * (6 * n))()
     strains = (C.c_void_p * n)()
     keep = []
+    dt = _field_dtype(precision)
+    named = []
     for i, sp in enumerate(samples):
-        nz, ny, nx = tuple(sp.phase.shape)
+        if getattr(sp.phase, "ndim", None) != 3:
+            raise ValueError(f"sample {i}: phase must be a 3D (nz, ny, nx) tensor")
+        nz, ny, nx = (int(v) for v in sp.phase.shape)
+        named.append((f"sample {i}: phase", _checked(sp.phase, f"sample {i}: phase", _uint8(), (nz, ny, nx),
+                                                     required=True)))
+        named.append((f"sample {i}: strain", _checked(sp.strain, f"sample {i}: strain", dt, (6, nz, ny, nx))))
+    addr = _addresses(named)
+    for i, sp in enumerate(samples):
+        nz, ny, nx = (int(v) for v in sp.phase.shape)
         grids[i] = FeGrid(nx, ny, nz)
-        phases[i] = _ptr(sp.phase)
+        phases[i] = addr[2 * i]
+        strains[i] = addr[2 * i + 1]
         m, k = _materials(sp.E, sp.nu)
         keep.append(k)
         mats[i] = m
@@ -338,7 +406,6 @@ def solve_batched(samples, tol, green="R", scheme="AS", precision="fp32", max_it
             raise ValueError("macro_strain needs 6 components")
         for q in range(6):
             macro[6 * i + q] = mv[q]
-        strains[i] = _ptr(sp.strain)
     desc = FeBatchDesc(n, grids, phases, mats, macro, strains)
     opt = _options(lib, precision, max_iter, ref_rule, ds_beta, E0, nu0, diverge_window, stream)
     res = (FeBatchResult * n)()
@@ -420,34 +487,71 @@ def _shape(x, c_in, c_out):
     return FeNNConvShape(nx, ny, nz, B, int(c_in), int(c_out))
 
 
+def _uint8():
+    import torch
+    return torch.uint8
+
+
+def _act5(x, name):
+    """A channel-last activation (B, nz, ny, nx, C) in bfloat16: its leading
+    shape and channel count (checked for rank and dtype)."""
+    import torch
+    if not isinstance(x, torch.Tensor) or x.ndim != 5:
+        raise ValueError(f"{name}: expected a (B, nz, ny, nx, C) tensor")
+    if x.dtype != torch.bfloat16:
+        raise ValueError(f"{name}: dtype {x.dtype}, expected torch.bfloat16")
+    return tuple(int(v) for v in x.shape[:4]), int(x.shape[4])
+
+
+def _weights(w):
+    import torch
+    if not isinstance(w, torch.Tensor) or w.ndim != 3 or int(w.shape[0]) != 27:
+        raise ValueError("w: expected a (27, c_in, c_out) tensor")
+    return int(w.shape[1]), int(w.shape[2])
+
+
 def conv3_forward(x, w, b=None, relu=True, stream=None):
     """fe_nn_conv3_forward on device tensors: x (B, nz, ny, nx, c_in) bfloat16,
     w (27, c_in, c_out) float32, b (c_out,) float32 -> y bfloat16."""
     import torch
+    lead, c = _act5(x, "x")
+    c_in, c_out = _weights(w)
+    px, pw, pb = _addresses([("x", _checked(x, "x", torch.bfloat16, lead + (c_in,), required=True)),
+                             ("w", _checked(w, "w", torch.float32, (27, c_in, c_out), required=True)),
+                             ("b", _checked(b, "b", torch.float32, (c_out,)))])
     lib = _bind_nn(load_library())
-    y = torch.empty(tuple(x.shape[:4]) + (int(w.shape[2]),), dtype=torch.bfloat16, device=x.device)
-    _check(lib.fe_nn_conv3_forward(C.byref(_shape(x, w.shape[1], w.shape[2])), _ptr(x), _ptr(w), _ptr(b),
-                                   1 if relu else 0, _ptr(y), stream), "fe_nn_conv3_forward")
+    y = torch.empty(lead + (c_out,), dtype=torch.bfloat16, device=x.device)
+    _check(lib.fe_nn_conv3_forward(C.byref(_shape(x, c_in, c_out)), px, pw, pb, 1 if relu else 0, _ptr(y), stream),
+           "fe_nn_conv3_forward")
     return y
 
 
 def conv3_backward_data(dy, w, y_mask=None, stream=None):
     import torch
+    lead, _ = _act5(dy, "dy")
+    c_in, c_out = _weights(w)
+    pdy, pm, pw = _addresses([("dy", _checked(dy, "dy", torch.bfloat16, lead + (c_out,), required=True)),
+                              ("y_mask", _checked(y_mask, "y_mask", torch.bfloat16, lead + (c_out,))),
+                              ("w", _checked(w, "w", torch.float32, (27, c_in, c_out), required=True))])
     lib = _bind_nn(load_library())
-    dx = torch.empty(tuple(dy.shape[:4]) + (int(w.shape[1]),), dtype=torch.bfloat16, device=dy.device)
-    _check(lib.fe_nn_conv3_backward_data(C.byref(_shape(dy, w.shape[1], w.shape[2])), _ptr(dy), _ptr(y_mask), _ptr(w),
-                                         _ptr(dx), stream), "fe_nn_conv3_backward_data")
+    dx = torch.empty(lead + (c_in,), dtype=torch.bfloat16, device=dy.device)
+    _check(lib.fe_nn_conv3_backward_data(C.byref(_shape(dy, c_in, c_out)), pdy, pm, pw, _ptr(dx), stream),
+           "fe_nn_conv3_backward_data")
     return dx
 
 
 def conv3_backward_weight(x, dy, y_mask=None, stream=None):
     import torch
+    lead, c_in = _act5(x, "x")
+    _, c_out = _act5(dy, "dy")
+    px, pdy, pm = _addresses([("x", _checked(x, "x", torch.bfloat16, lead + (c_in,), required=True)),
+                              ("dy", _checked(dy, "dy", torch.bfloat16, lead + (c_out,), required=True)),
+                              ("y_mask", _checked(y_mask, "y_mask", torch.bfloat16, lead + (c_out,)))])
     lib = _bind_nn(load_library())
-    c_in, c_out = int(x.shape[4]), int(dy.shape[4])
     dw = torch.empty((27, c_in, c_out), dtype=torch.float32, device=x.device)
     db = torch.empty((c_out,), dtype=torch.float32, device=x.device)
-    _check(lib.fe_nn_conv3_backward_weight(C.byref(_shape(x, c_in, c_out)), _ptr(x), _ptr(dy), _ptr(y_mask), _ptr(dw),
-                                           _ptr(db), stream), "fe_nn_conv3_backward_weight")
+    _check(lib.fe_nn_conv3_backward_weight(C.byref(_shape(x, c_in, c_out)), px, pdy, pm, _ptr(dw), _ptr(db), stream),
+           "fe_nn_conv3_backward_weight")
     return dw, db
 
 
@@ -499,7 +603,12 @@ class UNet:
     @staticmethod
     def _batch(phase, E, nu, macro):
         """phase: device uint8 (B, nz, ny, nx); E, nu: per-sample phase tables; macro (B, 6)."""
+        if getattr(phase, "ndim", None) != 4:
+            raise ValueError("phase: expected a (B, nz, ny, nx) tensor")
         B, nz, ny, nx = (int(v) for v in phase.shape)
+        _checked(phase, "phase", _uint8(), (B, nz, ny, nx), required=True)
+        if len(E) != B or len(nu) != B:
+            raise ValueError(f"E and nu need one phase table per sample ({B})")
         mats = (FeMaterials * B)()
         keep = []
         for s in range(B):
@@ -508,7 +617,7 @@ class UNet:
             keep.append(k)
         mac = np.ascontiguousarray(np.asarray(macro, dtype=np.float64).reshape(B, 6))
         keep.append(mac)
-        b = FeUnetBatch(FeGrid(nx, ny, nz), B, _ptr(phase), mats, mac.ctypes.data_as(C.POINTER(C.c_double)))
+        b = FeUnetBatch(FeGrid(nx, ny, nz), B, None, mats, mac.ctypes.data_as(C.POINTER(C.c_double)))
         keep.append(mats)
         return b, keep
 
@@ -516,28 +625,36 @@ class UNet:
         """Predicted strain, device float32 (B, 6, nz, ny, nx); returns (out, seconds)."""
         import torch
         b, keep = self._batch(phase, E, nu, macro)
+        shape = (b.batch, 6) + tuple(int(v) for v in phase.shape[1:])
+        _checked(out, "out", torch.float32, shape)
+        b.phase, _ = _addresses([("phase", phase), ("out", out)])
         if out is None:
-            out = torch.empty((b.batch, 6) + tuple(phase.shape[1:]), dtype=torch.float32, device=phase.device)
+            out = torch.empty(shape, dtype=torch.float32, device=phase.device)
+        pout = out.data_ptr()
         sec = C.c_double(0.0)
-        _check(self._lib.fe_unet_predict(self._h, C.byref(b), _ptr(out), C.byref(sec)), "fe_unet_predict")
+        _check(self._lib.fe_unet_predict(self._h, C.byref(b), pout, C.byref(sec)), "fe_unet_predict")
         del keep
         return out, sec.value
 
-    def loss_grad(self, phase, E, nu, macro, target):
+    def _target(self, b, phase, target):
         import torch
+        shape = (int(phase.shape[0]), 6) + tuple(int(v) for v in phase.shape[1:])
+        _checked(target, "target", (torch.float32, torch.bfloat16), shape, required=True)
+        b.phase, pt = _addresses([("phase", phase), ("target", target)])
+        return pt, 1 if target.dtype == torch.bfloat16 else 0
+
+    def loss_grad(self, phase, E, nu, macro, target):
         b, keep = self._batch(phase, E, nu, macro)
+        pt, is_bf16 = self._target(b, phase, target)
         loss = C.c_double(0.0)
-        _check(self._lib.fe_unet_loss_grad(self._h, C.byref(b), _ptr(target), 1 if target.dtype == torch.bfloat16 else 0,
-                                           C.byref(loss)), "fe_unet_loss_grad")
+        _check(self._lib.fe_unet_loss_grad(self._h, C.byref(b), pt, is_bf16, C.byref(loss)), "fe_unet_loss_grad")
         del keep
         return loss.value
 
     def train_step(self, phase, E, nu, macro, target):
-        import torch
         b, keep = self._batch(phase, E, nu, macro)
+        pt, is_bf16 = self._target(b, phase, target)
         loss = C.c_double(0.0)
-        _check(self._lib.fe_unet_train_step(self._h, C.byref(b), _ptr(target),
-                                            1 if target.dtype == torch.bfloat16 else 0, C.byref(loss)),
-               "fe_unet_train_step")
+        _check(self._lib.fe_unet_train_step(self._h, C.byref(b), pt, is_bf16, C.byref(loss)), "fe_unet_train_step")
         del keep
         return loss.value
