@@ -136,6 +136,68 @@ def time_to_tolerance(fe, torch, np, phase, E, nu, L, weights):
     return out
 
 
+def device_copy(fe, torch, nbytes=1 << 31, reps=5):
+    """Bandwidth of the library's streaming copy kernel (fe_stream_copy) on
+    2 GiB, read + write counted, best of ``reps`` per variant (plain and
+    non-temporal), timed with events on the stream it runs on; torch's copy_
+    beside it for reference."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    out = {}
+
+    def best_of(fn):
+        fn()
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn()
+            e1.record(st)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e-3)
+        return 2 * nbytes / best / 1e9
+
+    out["plain_gbs"] = round(best_of(lambda: fe.stream_copy(b, a, False, st.cuda_stream)), 1)
+    out["nontemporal_gbs"] = round(best_of(lambda: fe.stream_copy(b, a, True, st.cuda_stream)), 1)
+    out["torch_copy_gbs"] = round(best_of(lambda: b.copy_(a)), 1)
+    out["gbs"] = max(out["plain_gbs"], out["nontemporal_gbs"])
+    out["kernel"] = "fe_stream_copy of 2 GiB (read + write), best variant, best of 5"
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def fp64_rate(fe, torch, phase, E, nu, L, K, warmup, tti):
+    """The same workload with float64 fields (the paper's precision): K timed
+    iterations, and the time to eta <= 1e-6 from the plain start."""
+    eps = torch.empty((6, L, L, L), dtype=torch.float64, device="cuda")
+    with fe.Plan(L, green="R", scheme="AS", precision="fp64", max_iter=max(warmup, 1)) as plan:
+        plan.solve(phase, E, nu, MACRO, 1e-300, strain=eps)
+    torch.cuda.synchronize()
+    with fe.Plan(L, green="R", scheme="AS", precision="fp64", max_iter=K) as plan:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve(phase, E, nu, MACRO, 1e-300, strain=eps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    out = {"value": round(L ** 3 * K / wall, 1), "unit": "voxel-iter/s", "ms_per_step": round(wall / K * 1e3, 4),
+           "steps": K, "dtype": "f64"}
+    if tti:
+        with fe.Plan(L, green="R", scheme="AS", precision="fp64", max_iter=2000) as plan:
+            plan.solve(phase, E, nu, MACRO, 1e-6, strain=eps, history=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = plan.solve(phase, E, nu, MACRO, 1e-6, strain=eps, history=1)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        out["time_to_tol_1e-6"] = {"seconds": round(dt, 4), "iterations": r.iterations, "status": r.status,
+                                   "eta": r.eta, "C_12_12": float(r.mean_stress[5]) / 2.0}
+    del eps
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(L_sample: int, iters: int):
     """The FP64 oracle on the host cores: AS with the rotated operator on an
     L_sample^3 sample of the same recipe, `iters` iterations."""
@@ -167,8 +229,9 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tti", action="store_true", help="skip the time-to-tolerance solve")
-    ap.add_argument("--cpu-sample", type=int, default=96)
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 leg")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1412_8398_amd", "weights", "unet_warmstart.npy"),
                     help="trained warm-start network (.npy); the learned leg is skipped if absent")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -241,23 +304,16 @@ def main():
     step_bytes = sum(v for k, v in pb.items() if k != "pointwise")
     iter_gbs = step_bytes * K / wall / 1e9
 
-    # context for the roofline: what torch's device copy reaches on this GPU
-    # (copy_ of 2 GiB, read + write counted, best of 5; not the best possible
-    # copy, a reference point)
-    a = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
-    best = float("inf")
-    for _ in range(5):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.copy_(a)
-        e1.record()
-        e1.synchronize()
-        best = min(best, e0.elapsed_time(e1) * 1e-3)
-    copy_gbs = 2 * a.numel() * 4 / best / 1e9
-    del a, b
-    torch.cuda.empty_cache()
+    # context for the roofline: the bandwidth a plain copy attains on this GPU
+    copy = device_copy(fe, torch)
+
+    # the paper's precision: the same K iterations with float64 fields
+    fp64 = None
+    if not args.no_fp64:
+        del eps
+        torch.cuda.empty_cache()
+        fp64 = fp64_rate(fe, torch, phase, E, nu, L, K, args.warmup, not args.no_tti)
+        eps = None
 
     tti = None
     if not args.no_tti:
@@ -295,9 +351,9 @@ def main():
         "iteration_bytes_model": step_bytes,
         "iteration_gbs_model": round(iter_gbs, 1),
         "iteration_hbm_frac_model": round(iter_gbs / PEAK_HBM_GBS, 4),
-        "device_copy": {"gbs": round(copy_gbs, 1), "kernel": "torch copy_ of 2 GiB (read + write), best of 5",
-                         "dominant_kernel_frac": round(passes[dom]["gbs"] / copy_gbs, 4),
-                         "iteration_frac": round(iter_gbs / copy_gbs, 4)},
+        "device_copy": dict(copy, dominant_kernel_frac=round(passes[dom]["gbs"] / copy["gbs"], 4),
+                            iteration_frac=round(iter_gbs / copy["gbs"], 4)),
+        "fp64": fp64,
         "passes": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                    for k, v in passes.items()},
         "library_seconds": round(res.seconds, 4),

@@ -250,6 +250,17 @@ fe_status fe_solve_batched(fe_discretization disc, fe_scheme scheme, const fe_pl
                            const fe_batch_desc* desc, double tol, fe_batch_result* results,
                            double* seconds);
 
+/*
+ * Measurement reference: copy `bytes` (a multiple of 16) from src to dst,
+ * both device memory, 16-byte aligned and not overlapping, with the
+ * library's streaming copy kernel (16-byte vectors, all loads of a thread in
+ * flight before its stores; nontemporal != 0 marks loads and stores as
+ * streaming).  Asynchronous on hip_stream (NULL: the null stream).  The
+ * solver's passes are compared with the bandwidth this kernel reaches.
+ * Errors: FE_ERR_INVALID_ARG (NULL, size or alignment, overlap).
+ */
+fe_status fe_stream_copy(void* dst, const void* src, size_t bytes, int32_t nontemporal, void* hip_stream);
+
 /* Human-readable name of a status code (static string). */
 const char* fe_status_string(fe_status s);
 

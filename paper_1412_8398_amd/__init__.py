@@ -18,7 +18,7 @@ __all__ = [
     "FE_OK", "FE_NOT_CONVERGED", "FE_DIVERGED", "FE_ERR_INVALID_ARG", "FE_ERR_UNSUPPORTED",
     "FE_ERR_OOM", "FE_ERR_DEVICE", "GREEN", "SCHEME", "PRECISION", "FeError", "Plan", "Result",
     "load_library", "library_path", "status_string", "last_error", "BatchSampleSpec", "solve_batched",
-    "UNet", "conv3_forward", "conv3_backward_data", "conv3_backward_weight",
+    "UNet", "stream_copy", "conv3_forward", "conv3_backward_data", "conv3_backward_weight",
 ]
 
 FE_OK, FE_NOT_CONVERGED, FE_DIVERGED = 0, 1, 2
@@ -121,6 +121,8 @@ def load_library():
     lib.fe_solve_batched.argtypes = [C.c_int, C.c_int, C.POINTER(FePlanOptions), C.POINTER(FeBatchDesc), C.c_double,
                                      C.POINTER(FeBatchResult), C.POINTER(C.c_double)]
     lib.fe_solve_batched.restype = C.c_int
+    lib.fe_stream_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p]
+    lib.fe_stream_copy.restype = C.c_int
     lib.fe_status_string.argtypes = [C.c_int]
     lib.fe_status_string.restype = C.c_char_p
     lib.fe_last_error.argtypes = []
@@ -341,6 +343,22 @@ class Plan:
             raise FeError(s, "fe_effective_stiffness")
         del keep
         return np.array(Cv[:]).reshape(6, 6), list(its), s
+
+
+def stream_copy(dst, src, nontemporal=False, stream=None):
+    """fe_stream_copy between two device tensors of the same byte size (the
+    measurement reference for attainable HBM bandwidth)."""
+    import torch
+    for name, t in (("dst", dst), ("src", src)):
+        if not isinstance(t, torch.Tensor) or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous tensor")
+    nbytes = dst.numel() * dst.element_size()
+    if src.numel() * src.element_size() != nbytes:
+        raise ValueError("dst and src differ in size")
+    pd, ps = _addresses([("dst", dst), ("src", src)])
+    s = load_library().fe_stream_copy(pd, ps, nbytes, 1 if nontemporal else 0, stream)
+    if s != FE_OK:
+        raise FeError(s, "fe_stream_copy")
 
 
 @dataclass

@@ -217,3 +217,144 @@ def test_training_steps_reduce_the_loss():
     losses = [net.train_step(ph, E, nu, macro, tg) for _ in range(40)]
     assert losses[-1] < 0.5 * losses[0], losses
     net.close()
+
+
+# ---------------------------------------------------------------------------
+# against the plain float64 oracle (no storage rounding), and Adam
+# ---------------------------------------------------------------------------
+
+WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(__file__), "..", "paper_1412_8398_amd", "weights",
+                                     "unet_warmstart.npy")
+
+
+def _trained_case(shape=(32, 32, 32)):
+    """The committed warm-start network with bf16-representable convolution
+    weights (the head stays float32, as on the GPU), on two Boolean cells of
+    contrast 10 and 1000 under unit normal loads."""
+    flat = np.load(WEIGHTS).astype(np.float64)
+    p = U.unflatten(flat)
+    for name, _ in U.param_shapes():
+        if name.endswith(".w") and name != "head.w":
+            p[name] = bf16_round(p[name])
+    flat32 = U.flatten(p).astype(np.float32)
+    p = U.unflatten(flat32.astype(np.float64))
+    phases, E, nu, macro = [], [], [], []
+    for s in range(2):
+        ph, _ = boolean_spheres(shape, 4.0, 0.25, 40 + s)
+        phases.append(ph)
+        E.append([1.0, 10.0 ** (1 + 2 * s)])
+        nu.append([0.3, 0.25 + 0.05 * s])
+        m = np.zeros(6)
+        m[3 * s] = 1.0
+        macro.append(m)
+    return p, flat32, np.stack(phases), E, nu, np.array(macro)
+
+
+def _storage_noise(seed):
+    """The bf16 storage bound as noise: every stored tensor multiplied by
+    1 + d with d uniform in [-2^-9, 2^-9] (round to nearest with 8
+    significant bits changes a value by at most 2^-9 of itself)."""
+    g = np.random.default_rng(seed)
+    return lambda a: a * (1.0 + 2.0 ** -9 * g.uniform(-1.0, 1.0, np.shape(a)))
+
+
+def test_network_prediction_matches_the_plain_oracle():
+    """The GPU prediction against the float64 oracle without any storage
+    rounding.  The GPU stores every activation in bf16 (relative error at
+    most 2^-9 per stored value, plus fp32 accumulation, 2^-16 of the
+    absolute sums, negligible beside it).  Propagated through the network
+    to first order (relu is 1-Lipschitz, so a state that flips near zero
+    moves its value by no more than the perturbation), these errors add up
+    like independent noise; the oracle run with the storage bound injected
+    as noise (three draws) measures their size sigma, and the bound is
+    3 sigma.  A wrong tap, transpose, skip or pooling path moves the result
+    by O(1) of the fluctuation."""
+    p, flat32, phase, E, nu, macro = _trained_case()
+    net = fe.UNet()
+    net.set_params(flat32)
+    out, _ = net.predict(torch.from_numpy(phase).cuda(), E, nu, macro)
+    torch.cuda.synchronize()
+    got = _to_oracle(out.cpu().numpy().astype(np.float64))
+    x = U.features(phase, E, nu, macro)
+    ref, _ = U.forward(p, x, macro)
+    fl = np.linalg.norm(ref - macro[:, None, None, None, :])
+    sigma = max(np.linalg.norm(U.forward(p, x, macro, store=_storage_noise(sd))[0] - ref) for sd in (1, 2, 3))
+    err = np.linalg.norm(got - ref)
+    print(f"prediction vs plain oracle: {err / fl:.3e} of the fluctuation, storage-noise sigma {sigma / fl:.3e}",
+          flush=True)
+    assert sigma <= 0.05 * fl  # the bound is tight enough to catch an O(1) slip
+    assert err <= 3.0 * sigma
+    net.close()
+
+
+def test_network_gradients_match_the_plain_oracle():
+    """Loss and every parameter gradient against the float64 oracle without
+    storage rounding; the bound is 3 sigma per tensor, sigma from the
+    storage-bound noise injected into the forward and backward stores of the
+    oracle (as above, four draws).  The head bias has an exact gradient of zero (the mean
+    correction removes it)."""
+    p, flat32, phase, E, nu, macro = _trained_case(shape=(16, 16, 16))
+    r = np.random.default_rng(9)
+    target = macro[:, :, None, None, None] + 0.3 * r.standard_normal((2, 6) + phase.shape[1:])
+    net = fe.UNet()
+    net.set_params(flat32)
+    loss = net.loss_grad(torch.from_numpy(phase).cuda(), E, nu, macro, dev_f32(target))
+    grads = U.unflatten(net.get_grads().astype(np.float64))
+    x = U.features(phase, E, nu, macro)
+    tg = _to_oracle(target)
+    ref_loss, ref_g = U.loss_and_grad(p, x, macro, tg)
+    noisy = [U.loss_and_grad(p, x, macro, tg, store=_storage_noise(sd)) for sd in (3, 4, 5, 6)]
+    sig_loss = max(abs(nl - ref_loss) for nl, _ in noisy)
+    assert abs(loss - ref_loss) <= 3.0 * sig_loss + 1e-6 * ref_loss
+    bad = {}
+    for name, _ in U.param_shapes():
+        if name == "head.b":
+            continue
+        ref = np.linalg.norm(ref_g[name])
+        sig = max(np.linalg.norm(ng[name] - ref_g[name]) for _, ng in noisy)
+        err = np.linalg.norm(grads[name] - ref_g[name])
+        if not (err <= 3.0 * sig + 1e-6 * ref and sig <= 0.05 * ref):
+            bad[name] = (err / ref, sig / ref)
+    assert not bad, bad
+    net.close()
+
+
+@pytest.mark.parametrize("steps", [1, 10])
+def test_adam_update_matches_oracle(steps):
+    """fe_unet_train_step's parameter update against the oracle's Adam
+    (bias-corrected moments) fed with the gradients the GPU computed (read
+    back after each step), in float64.  The GPU keeps float32 master weights
+    and moments: per step the update lr mhat/(sqrt(vhat) + eps) carries a
+    relative rounding of a few float32 units (moments, bias corrections,
+    square root, division: at most 16 u, u = 2^-24, with the moments' own
+    error growing by 2 u per step), and the stored weight one rounding of
+    u |theta|.  Bound after n steps, per element:
+      |theta_gpu - theta_ref| <= n u |theta_ref|
+                                 + (16 + 2 n) u sum_k lr mabs_k / (sqrt(vhat_k) + eps)
+    with mabs the first moment of |g| (a missing bias correction, swapped
+    betas or eps inside the square root are off by far more)."""
+    _, flat32, phase, E, nu, macro = _net_case(seed=6)
+    r = np.random.default_rng(12)
+    target = macro[:, :, None, None, None] + 0.3 * r.standard_normal((2, 6) + phase.shape[1:])
+    lr, b1, b2, eps = 2e-3, 0.9, 0.999, 1e-8
+    net = fe.UNet(lr=lr, beta1=b1, beta2=b2, adam_eps=eps)
+    net.set_params(flat32)
+    ph, tg = torch.from_numpy(phase).cuda(), dev_f32(target)
+    theta = flat32.astype(np.float64)
+    st = U.AdamState(theta.size)
+    mabs = np.zeros_like(theta)
+    budget = np.zeros_like(theta)
+    u = 2.0 ** -24
+    for k in range(1, steps + 1):
+        net.train_step(ph, E, nu, macro, tg)
+        g = net.get_grads().astype(np.float64)
+        theta = U.adam_step(theta, g, st, lr=lr, beta1=b1, beta2=b2, eps=eps)
+        mabs = b1 * mabs + (1.0 - b1) * np.abs(g)
+        vhat = st.v / (1.0 - b2 ** k)
+        budget += lr * (mabs / (1.0 - b1 ** k)) / (np.sqrt(vhat) + eps)
+    got = net.get_params().astype(np.float64)
+    bound = steps * u * np.abs(theta) + (16 + 2 * steps) * u * budget
+    moved = np.abs(theta - flat32)
+    assert np.median(moved[moved > 0]) > 1e3 * np.median(bound[moved > 0])  # the update is far above the bound
+    assert np.all(np.abs(got - theta) <= bound), float(np.max(np.abs(got - theta) / np.maximum(bound, 1e-300)))
+    net.close()
