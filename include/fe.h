@@ -251,6 +251,34 @@ fe_status fe_solve_batched(fe_discretization disc, fe_scheme scheme, const fe_pl
                            double* seconds);
 
 /*
+ * fe_solve without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the plan's workspace (transform buffers, second iterate,
+ * partial sums, phase constants, twiddle and wave tables) is carved from a
+ * static device array of FE_STATIC_SCRATCH_BYTES that the library holds on
+ * every device it runs on until the process ends; no plan, no events, no
+ * pinned buffer.  Same kernels and results as fe_plan_create + fe_solve with
+ * the same options, restricted to:
+ *   - disc FE_GREEN_WP or FE_GREEN_ROT, scheme FE_DIRECT or FE_ACCELERATED
+ *     (FE_ERR_UNSUPPORTED otherwise);
+ *   - grids whose workspace fits the array: about 60 bytes per voxel in
+ *     float32 (96^3 fits), 120 in float64 (64^3 fits); larger grids give
+ *     FE_ERR_UNSUPPORTED before any device work;
+ *   - float32 plans iterate in float32 only (opt->refine is not used) and
+ *     report eta_verify_fp64 of the returned strain;
+ *   - opt->timing must be 0; the convergence check is not overlapped with
+ *     the next iteration; out->seconds is host time around the loop;
+ *   - out->strain must be a device buffer of 6*N plan-precision values.
+ * Runs on the current device and opt->hip_stream.  Calls that overlap on one
+ * device share the array and race: serialize them (one stream, or wait for
+ * a call to return before the next starts).  Arguments and errors as fe_solve.
+ */
+#define FE_STATIC_SCRATCH_BYTES (64u << 20)
+fe_status fe_solve_static(fe_grid grid, fe_discretization disc, fe_scheme scheme, const fe_plan_options* opt,
+                          const uint8_t* phase, fe_materials materials, const double macro_strain[6], double tol,
+                          const void* strain_init, fe_result* out);
+
+/*
  * Measurement reference: copy `bytes` (a multiple of 16) from src to dst,
  * both device memory, 16-byte aligned and not overlapping, with the
  * library's streaming copy kernel (16-byte vectors, all loads of a thread in

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <utility>
 #include <string>
@@ -413,6 +414,13 @@ template <>
 const Tables<float>& tables<float>(const fe_plan* p) { return p->t32; }
 template <>
 const Tables<double>& tables<double>(const fe_plan* p) { return p->t64; }
+
+template <typename T>
+static Tables<T>& tables_mut(fe_plan* p);
+template <>
+Tables<float>& tables_mut<float>(fe_plan* p) { return p->t32; }
+template <>
+Tables<double>& tables_mut<double>(fe_plan* p) { return p->t64; }
 
 template <typename T>
 static WaveTables<T> wave_tables(const fe_plan* p) {
@@ -854,7 +862,11 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     return verify_fp64<T>(p, eps, phase, ev);
   };
 
-  HIP_TRY(hipEventRecord(p->ev0, s));
+  // without events (the allocation-free entry point) the loop is timed on the
+  // host after a stream synchronisation and the convergence check is not
+  // overlapped with the next iteration
+  const auto host_t0 = std::chrono::steady_clock::now();
+  if (p->ev0) HIP_TRY(hipEventRecord(p->ev0, s));
   PassTimer tm(p, p->opt.timing != 0);
   fe_status status = FE_NOT_CONVERGED;
   double eta = NAN, prev_eta = INFINITY, mean[6] = {0, 0, 0, 0, 0, 0};
@@ -920,7 +932,7 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     // eta just read may reach tol (the last ratio extrapolated once, with a
     // factor 3 of margin) the queued iteration would be dropped, costing a
     // whole iteration instead of the host round trip it hides.
-    bool ahead = p->displacement && k < max_iter;
+    bool ahead = p->displacement && k < max_iter && p->evc;
     if (ahead && !hist.empty()) {
       const size_t nh = hist.size();
       const double r = nh >= 2 && hist[nh - 2] > 0.0 ? hist[nh - 1] / hist[nh - 2] : 1.0;
@@ -1051,11 +1063,16 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     fe_status ss = sync_iterate();
     if (ss != FE_OK) return ss;
   }
-  HIP_TRY(hipEventRecord(p->ev1, s));
-  HIP_TRY(hipEventSynchronize(p->ev1));
-  tm.flush();
   float ms_elapsed = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms_elapsed, p->ev0, p->ev1));
+  if (p->ev1) {
+    HIP_TRY(hipEventRecord(p->ev1, s));
+    HIP_TRY(hipEventSynchronize(p->ev1));
+    tm.flush();
+    HIP_TRY(hipEventElapsedTime(&ms_elapsed, p->ev0, p->ev1));
+  } else {
+    HIP_TRY(hipStreamSynchronize(s));
+    ms_elapsed = (float)(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - host_t0).count());
+  }
   HIP_TRY(hipGetLastError());
   for (int i = 0; i < 8; ++i) {
     out->pass_seconds[i] = tm.sec[i];
@@ -1106,6 +1123,169 @@ extern "C" fe_status fe_solve(fe_plan* p, const uint8_t* phase, fe_materials mat
   if (p->opt.precision == FE_FP64)
     return solve_impl<double>(p, phase, materials, macro_strain, tol, strain_init, out);
   return solve_impl<float>(p, phase, materials, macro_strain, tol, strain_init, out);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free solve: the workspace lives in a static device array
+// ---------------------------------------------------------------------------
+// Every device the library runs on holds its own copy of this array until the
+// process ends.  Host code never passes its name to a kernel or a copy: the
+// name is a host-side stand-in, the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[FE_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+fe_status scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FE_ERR_UNSUPPORTED, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FE_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return FE_OK;
+}
+
+// Carve the plan's buffers out of [base, base + cap) (nullptr base: count
+// only); returns the bytes needed.
+template <typename T>
+size_t carve_static(fe_plan* p, unsigned char* base, size_t cap, std::vector<std::vector<T>>* host_tables) {
+  size_t used = 0;
+  bool fits = true;
+  auto take = [&](size_t bytes) -> void* {
+    const size_t off = (used + 255) & ~(size_t)255;
+    used = off + bytes;
+    if (used > cap) fits = false;
+    return base && fits ? base + off : nullptr;
+  };
+  const Dims d = p->d;
+  const long long N = d.N;
+  const size_t spec = (size_t)spec_size(d);
+  const size_t lines = (size_t)d.Hp * p->grid.ny;
+  p->R = take(3 * (size_t)N * sizeof(T));
+  p->R2 = take(3 * (size_t)N * sizeof(T));
+  p->eps_alt = take(6 * (size_t)N * sizeof(T));
+  p->S = take(3 * spec * 2 * sizeof(T));
+  p->partials = static_cast<double*>(take(p->partial_count * sizeof(double)));
+  p->partials2 = static_cast<double*>(take((lines + 1) * sizeof(double)));
+  p->red = static_cast<double*>(take(16 * sizeof(double)));
+  p->flag = static_cast<int*>(take(sizeof(int)));
+  p->coef = take(256 * sizeof(PhaseCoef<double>));
+  p->coef64 = static_cast<PhaseCoef<double>*>(take(256 * sizeof(PhaseCoef<double>)));
+  Tables<T>& t = tables_mut<T>(p);
+  const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
+  for (int a = 0; a < 3; ++a) {
+    t.tw[a] = static_cast<cpx<T>*>(take(2 * (size_t)n[a] * sizeof(T)));
+    t.wave[a] = static_cast<T*>(take(2 * (size_t)n[a] * sizeof(T)));
+    if (host_tables) {
+      std::vector<double> tw = twiddles(n[a]), wv = wave_table(n[a], p->op);
+      host_tables->emplace_back(tw.begin(), tw.end());
+      host_tables->emplace_back(wv.begin(), wv.end());
+    }
+  }
+  return used;
+}
+}  // namespace
+
+extern "C" fe_status fe_solve_static(fe_grid g, fe_discretization disc, fe_scheme scheme, const fe_plan_options* opt,
+                                     const uint8_t* phase, fe_materials materials, const double macro_strain[6],
+                                     double tol, const void* strain_init, fe_result* out) {
+  fe_plan_options o;
+  fe_plan_options_default(&o);
+  if (opt) {
+    if (opt->struct_size != sizeof(fe_plan_options))
+      return fail(FE_ERR_INVALID_ARG, "fe_plan_options.struct_size is %u, expected %zu", opt->struct_size,
+                  sizeof(fe_plan_options));
+    o = *opt;
+  }
+  if (disc != FE_GREEN_WP && disc != FE_GREEN_ROT)
+    return fail(disc >= FE_GREEN_MS && disc <= FE_GREEN_CENTERED ? FE_ERR_UNSUPPORTED : FE_ERR_INVALID_ARG,
+                "fe_solve_static runs the WP and ROT operators");
+  if (scheme != FE_DIRECT && scheme != FE_ACCELERATED)
+    return fail(scheme == FE_CONJUGATE_GRADIENT ? FE_ERR_UNSUPPORTED : FE_ERR_INVALID_ARG,
+                "fe_solve_static runs the direct and accelerated schemes");
+  if (o.precision != FE_FP32 && o.precision != FE_FP64)
+    return fail(FE_ERR_INVALID_ARG, "unknown precision %d", (int)o.precision);
+  if (o.timing) return fail(FE_ERR_UNSUPPORTED, "fe_solve_static does not time passes (timing must be 0)");
+  if (o.max_iter < 0 || o.check_every < 1 || o.diverge_window < 0)
+    return fail(FE_ERR_INVALID_ARG, "max_iter, check_every or diverge_window out of range");
+  if (o.ref_rule != FE_REF_PAPER && o.ref_rule != FE_REF_EXPLICIT)
+    return fail(FE_ERR_INVALID_ARG, "unknown ref_rule %d", o.ref_rule);
+  if (o.ref_rule == FE_REF_PAPER && scheme == FE_DIRECT && !(o.ds_beta > 0.0 && std::isfinite(o.ds_beta)))
+    return fail(FE_ERR_INVALID_ARG, "ds_beta must be positive and finite");
+  if (o.ref_rule == FE_REF_EXPLICIT &&
+      !(std::isfinite(o.E0) && o.E0 > 0.0 && std::isfinite(o.nu0) && o.nu0 > -1.0 && o.nu0 < 0.5))
+    return fail(FE_ERR_INVALID_ARG, "explicit reference needs E0 > 0 and -1 < nu0 < 0.5");
+  const int n[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] <= 0) return fail(FE_ERR_INVALID_ARG, "grid dimension %d is %d", a, n[a]);
+    if (!(a == 2 ? supported_z_length(n[a]) : supported_length(n[a])))
+      return fail(FE_ERR_UNSUPPORTED, "grid dimension %d = %d: need 2^a or 3*2^a in [4, 1024] (nz: or 1)", a, n[a]);
+  }
+  if (!phase || !macro_strain || !out) return fail(FE_ERR_INVALID_ARG, "phase, macro_strain or out is NULL");
+  if (!out->strain) return fail(FE_ERR_INVALID_ARG, "fe_solve_static needs out->strain (it keeps no iterate)");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FE_ERR_INVALID_ARG, "tol must be finite and > 0");
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(macro_strain[i])) return fail(FE_ERR_INVALID_ARG, "macro_strain[%d] is not finite", i);
+  if (out->history_capacity < 0) return fail(FE_ERR_INVALID_ARG, "history_capacity < 0");
+  if (out->history_capacity > 0 && !out->eta_history && !out->mean_stress_history)
+    return fail(FE_ERR_INVALID_ARG, "eta_history and mean_stress_history are NULL with a positive capacity");
+  fe_status st = validate_materials(materials);
+  if (st != FE_OK) return st;
+
+  fe_plan p;  // no allocation: every buffer is a slice of the static array, no events
+  p.grid = g;
+  p.disc = disc;
+  p.scheme = scheme;
+  p.opt = o;
+  p.opt.refine = 0;  // float32 runs iterate in float32 only (re-anchoring needs more workspace)
+  p.stream = (hipStream_t)o.hip_stream;
+  p.op = disc == FE_GREEN_WP ? OP_WP : OP_ROT;
+  p.displacement = true;
+  p.d = make_dims(g.nx, g.ny, g.nz);
+  const long long db = (p.d.N + kThreads - 1) / kThreads;
+  p.div_blocks = (int)(db > kMaxReduceBlocks ? kMaxReduceBlocks : db);
+  p.partial_count = (size_t)kMaxReduceBlocks * 7;
+  const bool f64 = o.precision == FE_FP64;
+  const size_t need = f64 ? carve_static<double>(&p, nullptr, SIZE_MAX, nullptr)
+                          : carve_static<float>(&p, nullptr, SIZE_MAX, nullptr);
+  if (need > (size_t)FE_STATIC_SCRATCH_BYTES)
+    return fail(FE_ERR_UNSUPPORTED, "grid %dx%dx%d needs %zu bytes of workspace; the static scratch holds %zu",
+                g.nx, g.ny, g.nz, need, (size_t)FE_STATIC_SCRATCH_BYTES);
+  HIP_TRY(hipGetDevice(&p.device));
+  unsigned char* base = nullptr;
+  st = scratch_address(p.device, &base);
+  if (st != FE_OK) return st;
+  double h_red[16];
+  p.h_red = h_red;
+  std::vector<std::vector<double>> h64;
+  std::vector<std::vector<float>> h32;
+  if (f64)
+    carve_static<double>(&p, base, FE_STATIC_SCRATCH_BYTES, &h64);
+  else
+    carve_static<float>(&p, base, FE_STATIC_SCRATCH_BYTES, &h32);
+  for (int a = 0; a < 3; ++a) {
+    if (f64) {
+      HIP_TRY(hipMemcpyAsync(p.t64.tw[a], h64[2 * a].data(), h64[2 * a].size() * 8, hipMemcpyHostToDevice, p.stream));
+      HIP_TRY(hipMemcpyAsync(p.t64.wave[a], h64[2 * a + 1].data(), h64[2 * a + 1].size() * 8, hipMemcpyHostToDevice,
+                             p.stream));
+    } else {
+      HIP_TRY(hipMemcpyAsync(p.t32.tw[a], h32[2 * a].data(), h32[2 * a].size() * 4, hipMemcpyHostToDevice, p.stream));
+      HIP_TRY(hipMemcpyAsync(p.t32.wave[a], h32[2 * a + 1].data(), h32[2 * a + 1].size() * 4, hipMemcpyHostToDevice,
+                             p.stream));
+    }
+  }
+  st = f64 ? solve_impl<double>(&p, phase, materials, macro_strain, tol, strain_init, out)
+           : solve_impl<float>(&p, phase, materials, macro_strain, tol, strain_init, out);
+  (void)hipStreamSynchronize(p.stream);  // the host tables and h_red outlive every queued copy
+  return st;
 }
 
 extern "C" fe_status fe_effective_stiffness(fe_plan* p, const uint8_t* phase, fe_materials materials, double tol,
