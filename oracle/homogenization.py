@@ -41,6 +41,20 @@ Readings of the paper taken here:
   R6  positions are in voxel units (spacing 1).
   R7  with more than two phases, or unequal Poisson ratios, eqs. (17)/(18)
       take the smallest and largest phase bulk and shear moduli.
+  R9  eq. (15), the symmetrised alternative to eq. (14) for the continuous
+      operator, is read with -q the grid partner of q: the mode whose DFT
+      coefficient is the conjugate of q's for a real field, i.e. -q with
+      every Nyquist component kept at +pi (a component -pi is not a grid
+      mode).  At a mode with some q_i = pi the operator is the mean of the
+      continuous operator of eq. (8) at q and at that partner (real, so the
+      conjugate in eq. (15) changes nothing); the inverse transform is then
+      real.  Read literally, with -q the negated vector, eq. (15) would equal
+      G(q) (eq. (8) is real and even) and change nothing.  This variant is
+      operator "MSS"; everywhere else it is "MS".  This operator does not
+      impose equilibrium at those modes (its fixed point leaves
+      conj(k).sigma(q) nonzero there: with every mode in eq. (43), eta
+      stalls at 0.26 on a 6x8x10 Voronoi cell), so for "MSS" the sum of
+      eq. (43) runs over the other modes, where it is the continuous operator.
   R8  the conjugate-gradient solver that §1 and §7 name as another use of
       the modified operators is read as plain (Hestenes-Stiefel) conjugate
       gradients on the discrete problem of eq. (19) for the strain
@@ -59,7 +73,7 @@ import os
 import numpy as np
 import scipy.fft as _sfft
 
-OPERATORS = ("MS", "C", "W", "R")
+OPERATORS = ("MS", "C", "W", "R", "MSS")
 SCHEMES = ("DS", "AS")
 
 # ----------------------------------------------------------------------------
@@ -232,7 +246,7 @@ def wave_vector_at(op, shape, index):
 def _wave_vector_from_modes(op, ms, Ls):
     full = np.broadcast_shapes(*(np.shape(m) for m in ms))
     k = np.zeros((3,) + tuple(full), dtype=np.complex128)
-    if op == "MS":
+    if op in ("MS", "MSS"):
         for a in range(3):
             k[a] = 1j * (2.0 * np.pi * ms[a] / Ls[a])
     elif op == "C":
@@ -282,7 +296,7 @@ def special_modes(op, shape):
     nyq = [np.broadcast_to((L % 2 == 0) & (m == L // 2), full) for m, L in zip(ms, Ls)]
     zero = [np.broadcast_to(m == 0, full) for m in ms]
     nonzero_q = ~(zero[0] & zero[1] & zero[2])
-    if op == "MS":
+    if op in ("MS", "MSS"):
         return (nyq[0] | nyq[1] | nyq[2]) & nonzero_q
     if op == "C":
         return (nyq[0] | zero[0]) & (nyq[1] | zero[1]) & (nyq[2] | zero[2]) & nonzero_q
@@ -332,7 +346,29 @@ def _green_plan(op, ref: Reference, shape):
     ordinary = ~special
     ordinary[0, 0, 0] = False
     Ainv = np.linalg.inv(A[ordinary])
-    plan = (k, kc, special, ordinary, Ainv)
+    partner = None
+    if op == "MSS" and special.any():
+        # eq. (15) (R9): at the special modes, k at q and at the grid partner
+        # of q (-q with the Nyquist components kept at +pi), and A^-1 at both
+        (mx, my, mz), (nx, ny, nz) = mode_grid(shape)
+        ms = [np.broadcast_to(m, shape) for m in (mx, my, mz)]
+        Ls = (nx, ny, nz)
+        kp = np.zeros((3,) + tuple(shape), dtype=np.complex128)
+        for a in range(3):
+            nyq_a = (Ls[a] % 2 == 0) & (ms[a] == Ls[a] // 2)
+            mp = np.where(nyq_a, ms[a], -ms[a])
+            kp[a] = 1j * (2.0 * np.pi * mp / Ls[a])
+        kq, kpq = k[:, special], kp[:, special]
+
+        def inv_a(kk):
+            kkc = np.conj(kk)
+            k2s = np.sum(np.abs(kk) ** 2, axis=0)
+            Am = (lam0 * np.einsum("jm,lm->mjl", kkc, kk) + mu0 * np.einsum("jm,lm->mjl", kk, kkc)
+                  + mu0 * k2s[:, None, None] * _I3)
+            return np.linalg.inv(Am)
+
+        partner = (kq, kpq, inv_a(kq), inv_a(kpq))
+    plan = (k, kc, special, ordinary, Ainv, partner)
     _GREEN_CACHE[key] = plan
     return plan
 
@@ -351,7 +387,7 @@ def green_apply(op, ref: Reference, tau_hat, shape=None):
     if shape is None:
         shape = tau_hat.shape[2:]
     shape = tuple(shape)
-    k, kc, special, ordinary, Ainv = _green_plan(op, ref, shape)
+    k, kc, special, ordinary, Ainv, partner = _green_plan(op, ref, shape)
     # b_j = sum_i conj(k_i) tau_ij
     b = np.einsum("i...,ij...->j...", kc, tau_hat)
     u = np.zeros(shape + (3,), dtype=np.complex128)
@@ -362,6 +398,16 @@ def green_apply(op, ref: Reference, tau_hat, shape=None):
     out = -eps
     if op == "MS" and special.any():
         out[:, :, special] = compliance_apply(ref, tau_hat[:, :, special])
+    if op == "MSS" and special.any():
+        # eq. (15): the mean of the continuous operator at q and at its partner
+        ts = tau_hat[:, :, special]  # (3, 3, M)
+        g = np.zeros_like(ts)
+        for kk, Ai in ((partner[0], partner[2]), (partner[1], partner[3])):
+            b = np.einsum("im,ijm->jm", np.conj(kk), ts)
+            u = -np.einsum("mjl,lm->jm", Ai, b)
+            e = 0.5 * (np.einsum("im,jm->ijm", kk, u) + np.einsum("jm,im->ijm", kk, u))
+            g += 0.5 * (-e)
+        out[:, :, special] = g
     # C and R special modes: G' = 0 (already 0 since u = 0 there); q = 0: 0.
     out[:, :, 0, 0, 0] = 0.0
     return out
@@ -472,6 +518,8 @@ def equilibrium_norm(op, sigma):
     s_hat = forward_dft(sigma)
     kc = np.conj(wave_vector(op, shape))
     div = np.einsum("i...,ij...->j...", kc, s_hat)
+    if op == "MSS":  # R9: equilibrium is imposed off the Nyquist modes only
+        div[:, special_modes(op, shape)] = 0.0
     num = math.sqrt(float(np.sum(np.abs(div) ** 2)))
     den = float(np.linalg.norm(s_hat[:, :, 0, 0, 0]))
     return num / den
