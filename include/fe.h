@@ -55,9 +55,17 @@ typedef enum {
   FE_GREEN_MS = 0,      /* continuous operator, k = i q, eqs. (8), (14)       */
   FE_GREEN_WP = 1,      /* Willot-Pellegrini, k = exp(i q) - 1, eq. (21)       */
   FE_GREEN_ROT = 2,     /* rotated grid, k of eq. (36), special modes eq. (41)  */
-  FE_GREEN_CENTERED = 3 /* centered differences, k = i sin q (§4.2); zero where
+  FE_GREEN_CENTERED = 3, /* centered differences, k = i sin q (§4.2); zero where
                            every q_i is 0 or pi, eq. (29).  Six-component form
-                           like FE_GREEN_MS (no float64 re-anchoring).       */
+                           like FE_GREEN_MS.                                 */
+  FE_GREEN_MS_SYMMETRIZED = 4 /* continuous operator with the symmetrised
+                           Nyquist rule of eq. (15) instead of eq. (14): at a
+                           mode with some q_i = pi, the mean of eq. (8) at q
+                           and at its grid partner (-q with the Nyquist
+                           components kept at +pi), a real operator equal at
+                           the two; eta (eq. (43)) is summed over the other
+                           modes, where equilibrium is imposed.  The fixed
+                           point depends on C0 (eq. (14)'s does not).       */
 } fe_discretization;
 
 typedef enum {
@@ -65,19 +73,26 @@ typedef enum {
   FE_ACCELERATED = 1,         /* eq. (16)                                           */
   FE_CONJUGATE_GRADIENT = 2   /* conjugate gradients on the discrete problem of
                                  eq. (19), the use of the modified operators that
-                                 §1 and §7 name: WP and ROT only (FE_ERR_UNSUPPORTED
-                                 at plan creation otherwise), reference medium of
-                                 eq. (17) (FE_REF_PAPER), start eps_bar only
-                                 (strain_init must be NULL).  The true residual
-                                 is recomputed when the recursive one reaches
-                                 tol or stalls, and the iteration restarts from
-                                 it on drift.  Float32 plans with refine (the
-                                 default) keep the displacement in float64 and
-                                 form every true residual in float64; the
-                                 float32 strain returned must verify <= tol
-                                 (else FE_NOT_CONVERGED).  Without refine a
-                                 restart gaining less than a factor 2 ends the
-                                 run (FE_NOT_CONVERGED, float32 floor).        */
+                                 §1 and §7 name; reference medium of eq. (17)
+                                 (FE_REF_PAPER), start eps_bar only (strain_init
+                                 must be NULL); not with FE_GREEN_MS_SYMMETRIZED
+                                 (FE_ERR_UNSUPPORTED at plan creation).
+                                 WP and ROT (corner displacement, preconditioned
+                                 by the reference medium's operator): the true
+                                 residual is recomputed when the recursive one
+                                 reaches tol or stalls, and the iteration
+                                 restarts from it on drift.  Float32 plans with
+                                 refine (the default) keep the displacement in
+                                 float64 and form every true residual in
+                                 float64; the float32 strain returned must
+                                 verify <= tol (else FE_NOT_CONVERGED).  Without
+                                 refine a restart gaining less than a factor 2
+                                 ends the run (FE_NOT_CONVERGED, float32 floor).
+                                 MS and CENTERED (six-component form): CG on the
+                                 strain in the inner product sum a:C0:b, eta of
+                                 the iterate every iteration; float32 plans run
+                                 in float32 (no 5% gain in eta over 100
+                                 iterations: FE_NOT_CONVERGED).               */
 } fe_scheme;
 
 /* Arithmetic of the fields, FFTs and Green operator.  Reductions (eta, mean
@@ -109,10 +124,10 @@ typedef struct {
                              increases of eta (default 50; 0 disables)          */
   int32_t timing;         /* nonzero: time every pass with HIP events on the plan's
                              stream and report it in fe_result.pass_seconds     */
-  int32_t refine;         /* FP32 plans, WP/ROT operators: when the float32 iteration
-                             stalls (or reaches tol while the float64 check does
-                             not), re-anchor in float64 and iterate in float32 on
-                             the correction (default 1; 0 = plain float32)     */
+  int32_t refine;         /* FP32 plans: when the float32 iteration stalls (or
+                             reaches tol while the float64 check does not),
+                             re-anchor in float64 and iterate in float32 on the
+                             correction (default 1; 0 = plain float32)         */
   void* hip_stream;       /* hipStream_t to run on; NULL = the null stream        */
 } fe_plan_options;
 

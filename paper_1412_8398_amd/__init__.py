@@ -24,7 +24,7 @@ __all__ = [
 FE_OK, FE_NOT_CONVERGED, FE_DIVERGED = 0, 1, 2
 FE_ERR_INVALID_ARG, FE_ERR_UNSUPPORTED, FE_ERR_OOM, FE_ERR_DEVICE = -1, -2, -3, -4
 
-GREEN = {"MS": 0, "WP": 1, "W": 1, "ROT": 2, "R": 2, "C": 3, "CENTERED": 3}
+GREEN = {"MS": 0, "WP": 1, "W": 1, "ROT": 2, "R": 2, "C": 3, "CENTERED": 3, "MSS": 4, "MS_SYMMETRIZED": 4}
 SCHEME = {"DS": 0, "direct": 0, "AS": 1, "accelerated": 1, "CG": 2, "conjugate_gradient": 2}
 PRECISION = {"fp64": 0, "fp32": 1}
 REF_RULE = {"paper": 0, "explicit": 1}

@@ -127,6 +127,14 @@ struct fe_plan {
   double* d64 = nullptr;     // float64 divergence / displacement, 3 planes
   cpx<double>* s64 = nullptr;  // float64 half spectra, 3 components
   void* dlt_alt = nullptr;     // second correction buffer (fused update + divergence)
+  // six-component form, float64 work (allocated on first use): a strain, a
+  // transform input/output and the half spectra (6 planes each); and for
+  // float32 re-anchoring the anchor's divergence spectrum (6 half spectra of
+  // the plan precision: conj(k).sigma at q and at its mirror)
+  double* six64a = nullptr;
+  double* six64b = nullptr;
+  cpx<double>* six64s = nullptr;
+  void* dbase6 = nullptr;
   // displacement form: second iterate and divergence buffers (allocated on first use)
   void* eps_alt = nullptr;
   void* R2 = nullptr;
@@ -228,12 +236,12 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
                   sizeof(fe_plan_options));
     o = *opt;
   }
-  if (disc < FE_GREEN_MS || disc > FE_GREEN_CENTERED)
+  if (disc < FE_GREEN_MS || disc > FE_GREEN_MS_SYMMETRIZED)
     return fail(FE_ERR_INVALID_ARG, "unknown discretization %d", (int)disc);
   if (scheme != FE_DIRECT && scheme != FE_ACCELERATED && scheme != FE_CONJUGATE_GRADIENT)
     return fail(FE_ERR_INVALID_ARG, "unknown scheme %d", (int)scheme);
-  if (scheme == FE_CONJUGATE_GRADIENT && disc != FE_GREEN_WP && disc != FE_GREEN_ROT)
-    return fail(FE_ERR_UNSUPPORTED, "conjugate gradients run on the WP and ROT operators (displacement form)");
+  if (scheme == FE_CONJUGATE_GRADIENT && disc == FE_GREEN_MS_SYMMETRIZED)
+    return fail(FE_ERR_UNSUPPORTED, "conjugate gradients need a projection operator (eq. (15)'s Nyquist rule is not)");
   if (o.precision != FE_FP32 && o.precision != FE_FP64)
     return fail(FE_ERR_INVALID_ARG, "unknown precision %d", (int)o.precision);
   if (o.max_iter < 0) return fail(FE_ERR_INVALID_ARG, "max_iter must be >= 0");
@@ -259,7 +267,11 @@ extern "C" fe_status fe_plan_create(fe_grid g, fe_discretization disc, fe_scheme
   p->scheme = scheme;
   p->opt = o;
   p->stream = (hipStream_t)o.hip_stream;
-  p->op = disc == FE_GREEN_MS ? OP_MS : disc == FE_GREEN_WP ? OP_WP : disc == FE_GREEN_ROT ? OP_ROT : OP_C;
+  p->op = disc == FE_GREEN_MS    ? OP_MS
+          : disc == FE_GREEN_WP  ? OP_WP
+          : disc == FE_GREEN_ROT ? OP_ROT
+          : disc == FE_GREEN_CENTERED ? OP_C
+                                      : OP_MSS;
   p->displacement = p->op == OP_WP || p->op == OP_ROT;
   p->d = make_dims(g.nx, g.ny, g.nz);
   long long db = (p->d.N + kThreads - 1) / kThreads;
@@ -319,7 +331,8 @@ extern "C" void fe_plan_destroy(fe_plan* p) {
   (void)hipSetDevice(p->device);
   void* bufs[] = {p->eps_ws, p->R,      p->S,       p->partials, p->partials2, p->red,     p->flag,   p->coef,
                   p->coef64, p->dlt,    p->rfield,  p->dsig_hi,  p->d64,       p->s64,     p->dlt_alt, p->eps_alt,
-                  p->R2,     p->cg,     p->coef_cg, p->cgs,      p->cg64,      p->coef_cg64};
+                  p->R2,     p->cg,     p->coef_cg, p->cgs,      p->cg64,      p->coef_cg64, p->six64a,  p->six64b,
+                  p->six64s, p->dbase6};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_tables(p->t32);
@@ -428,6 +441,15 @@ static WaveTables<T> wave_tables(const fe_plan* p) {
   return WaveTables<T>{t.wave[0], t.wave[1], t.wave[2]};
 }
 
+// float64 work buffers of the six-component form (verification, re-anchoring)
+static fe_status six64_workspace(fe_plan* p) {
+  const size_t N = (size_t)p->d.N, spec = (size_t)spec_size(p->d);
+  if (!p->six64a) HIP_TRY(dmalloc(p, (void**)&p->six64a, 6 * N * sizeof(double)));
+  if (!p->six64b) HIP_TRY(dmalloc(p, (void**)&p->six64b, 6 * N * sizeof(double)));
+  if (!p->six64s) HIP_TRY(dmalloc(p, (void**)&p->six64s, 6 * spec * sizeof(cpx<double>)));
+  return FE_OK;
+}
+
 // eta and <sigma> of the current strain (float64 arithmetic from a strain of
 // storage type TS), via the spectral 6-component path for MS or the
 // corner/backward stencil otherwise.  Requires a float64 workspace for MS when
@@ -446,17 +468,14 @@ static fe_status verify_fp64(fe_plan* p, const TS* eps, const uint8_t* phase, do
     *eta_out = std::sqrt(p->h_red[0] / (double)d.N) / frob(ms);
     return FE_OK;
   }
-  double *e64 = nullptr, *r64 = nullptr;
-  cpx<double>* s64 = nullptr;
-  const size_t spec = (size_t)spec_size(d);
-  if (hipMalloc(&e64, 6 * (size_t)d.N * 8) != hipSuccess || hipMalloc(&r64, 6 * (size_t)d.N * 8) != hipSuccess ||
-      hipMalloc(&s64, 6 * spec * sizeof(cpx<double>)) != hipSuccess) {
-    if (e64) (void)hipFree(e64);
-    if (r64) (void)hipFree(r64);
+  if (six64_workspace(p) != FE_OK) {  // no room for the float64 work: no verification
     (void)hipGetLastError();
     *eta_out = NAN;
     return FE_OK;
   }
+  double* e64 = p->six64a;
+  double* r64 = p->six64b;
+  cpx<double>* s64 = p->six64s;
   Launch<double>::convert_to(e64, eps, sizeof(TS) == 8, 6 * d.N, s);
   Launch<double>::tau6(e64, phase, p->coef64, r64, 1, p->partials, p->div_blocks, d, s);
   launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
@@ -467,9 +486,6 @@ static fe_status verify_fp64(fe_plan* p, const TS* eps, const uint8_t* phase, do
   launch_reduce(p->partials2, nblk, 1, p->red + 8, s);
   HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  (void)hipFree(e64);
-  (void)hipFree(r64);
-  (void)hipFree(s64);
   double ms[6];
   for (int i = 0; i < 6; ++i) ms[i] = p->h_red[1 + i] / (double)d.N;
   *eta_out = std::sqrt(p->h_red[8]) / ((double)d.N * frob(ms));
@@ -707,6 +723,124 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
   return status;
 }
 
+// Conjugate gradients in the six-component form (MS, C): the iterate is the
+// strain eps = eps_bar + e with e compatible and of zero mean; with
+// B(x) = G' * (C : x) (a C0-orthogonal projection after C, self-adjoint and
+// positive in <a, b> = sum_x a : C0 : b on compatible fields) the fluctuation
+// solves B(e) = -B(eps_bar).  Per iteration: B(p) by the transform passes
+// with no applied strain, <p, B(p)>, the step, the direction, and eta^k of
+// eps (eq. (43), spectral).  The scalars stay on the device; the host reads
+// eta.  Float32 plans run in float32 (no refinement): no 5% gain in eta over
+// 100 iterations ends the run at the float32 floor (FE_NOT_CONVERGED).
+template <typename T>
+static fe_status solve_cg6(fe_plan* p, const uint8_t* phase, const PhaseCoef<T>* coef, const GreenConst<T>& g,
+                           const RefMedium& ref, const double* macro, T* eps, double tol, fe_result* out) {
+  hipStream_t s = p->stream;
+  const Dims d = p->d;
+  const long long N = d.N, n6 = 6 * N;
+  const Tables<T>& tb = tables<T>(p);
+  const WaveTables<T> wt = wave_tables<T>(p);
+  if (!p->cgs) HIP_TRY(dmalloc(p, (void**)&p->cgs, 32 * sizeof(double)));
+  if (!p->cg) HIP_TRY(dmalloc(p, &p->cg, 3 * (size_t)n6 * sizeof(T)));
+  T* r = static_cast<T*>(p->cg);
+  T* pd = r + n6;
+  T* Q = pd + n6;
+  T* R = static_cast<T*>(p->R);
+  cpx<T>* S = static_cast<cpx<T>*>(p->S);
+  double* cgs = p->cgs;
+  GreenConst<T> gz = g;  // B(x): no applied strain
+  for (int i = 0; i < 6; ++i) gz.macro[i] = T(0);
+  // Qout = (negate ? B(x) : -B(x)), dst = <dotx, Qout> (dotx NULL: <Qout, Qout>)
+  auto apply_b = [&](const T* x, T* Qout, const T* dotx, int negate, double* dst) {
+    Launch<T>::tau6(x, phase, coef, R, 1, nullptr, p->div_blocks, d, s);
+    Launch<T>::zr2c(R, S, 6, d, tb.tw[2], s);
+    Launch<T>::yfft(S, 6, d, tb.tw[1], 0, s);
+    Launch<T>::xgreen6(S, d, tb.tw[0], wt, gz, p->op, s);
+    Launch<T>::yfft(S, 6, d, tb.tw[1], 1, s);
+    Launch<T>::zc2r(S, R, 6, d, tb.tw[2], s);
+    const int nb = Launch<T>::cg6_take(R, Qout, dotx, negate, d, ref.lam0, ref.mu0, p->partials, s);
+    launch_reduce(p->partials, nb, 1, dst, s);
+  };
+  double mean[6] = {0, 0, 0, 0, 0, 0};
+  auto eta_now = [&](double* e) -> fe_status {
+    Launch<T>::tau6(eps, phase, coef, R, 1, p->partials, p->div_blocks, d, s);
+    launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
+    Launch<T>::zr2c(R, S, 6, d, tb.tw[2], s);
+    Launch<T>::yfft(S, 6, d, tb.tw[1], 0, s);
+    const int xblk = Launch<T>::xeta6(S, d, tb.tw[0], wt, p->partials2, p->op, s);
+    launch_reduce(p->partials2, xblk, 1, p->red + 8, s);
+    HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < 6; ++i) mean[i] = p->h_red[1 + i] / (double)N;
+    *e = std::sqrt(p->h_red[8]) / ((double)N * frob(mean));
+    return FE_OK;
+  };
+  auto record = [&](int kk, double e) {
+    if (kk >= out->history_capacity) return;
+    if (out->eta_history) out->eta_history[kk] = e;
+    if (out->mean_stress_history)
+      for (int i = 0; i < 6; ++i) out->mean_stress_history[6 * kk + i] = mean[i];
+  };
+  const auto host_t0 = std::chrono::steady_clock::now();
+  HIP_TRY(hipMemsetAsync(cgs, 0, 32 * sizeof(double), s));
+  Launch<T>::fill_macro(eps, N, macro, s);
+  apply_b(eps, r, nullptr, 0, cgs + 0);  // r = -B(eps_bar), <r, r>
+  Launch<T>::cg_dir(pd, r, n6, cgs, 1, s);
+  fe_status status = FE_NOT_CONVERGED;
+  double eta = NAN, best = INFINITY;
+  int k = 0, best_k = 0;
+  for (;; ++k) {
+    fe_status es = eta_now(&eta);
+    if (es != FE_OK) return es;
+    record(k, eta);
+    if (!std::isfinite(eta)) {
+      status = FE_DIVERGED;
+      break;
+    }
+    if (eta <= tol) {
+      status = FE_OK;
+      break;
+    }
+    if (k >= p->opt.max_iter) break;
+    if (eta < 0.95 * best) {
+      best = eta;
+      best_k = k;
+    } else if (sizeof(T) == 4 && k - best_k >= 100) {
+      break;  // float32 floor
+    }
+    apply_b(pd, Q, pd, 1, cgs + 16);  // Q = B(p), <p, Q>
+    const int nb = Launch<T>::cg6_step(eps, pd, r, Q, N, ref.lam0, ref.mu0, cgs, p->partials, s);
+    launch_reduce(p->partials, nb, 1, cgs + 0, s);
+    Launch<T>::cg_dir(pd, r, n6, cgs, 0, s);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  const double seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - host_t0).count();
+  for (int i = 0; i < 8; ++i) {
+    out->pass_seconds[i] = 0.0;
+    out->pass_launches[i] = 0;
+  }
+  out->refinements = 0;
+  if (out->stress) Launch<T>::stress(eps, phase, coef, static_cast<T*>(out->stress), N, s);
+  double ev = eta;
+  if (sizeof(T) == 4) {
+    fe_status vs = verify_fp64<T>(p, eps, phase, &ev);
+    if (vs != FE_OK) return vs;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  out->iterations = k;
+  out->eta = eta;
+  out->eta_verify_fp64 = ev;
+  out->seconds = seconds;
+  for (int i = 0; i < 6; ++i) out->mean_stress[i] = mean[i];
+  if (status == FE_NOT_CONVERGED)
+    fail(status, "not converged after %d iterations (eta = %.3e, tol = %.3e)", k, eta, tol);
+  else if (status == FE_DIVERGED)
+    fail(status, "diverged at iteration %d (eta = %.3e)", k, eta);
+  return status;
+}
+
 template <typename T>
 static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials& mat, const double* macro, double tol,
                             const void* strain_init, fe_result* out) {
@@ -755,7 +889,9 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     if (!p->eps_ws) HIP_TRY(dmalloc(p, &p->eps_ws, 6 * (size_t)N * sizeof(T)));
     eps = static_cast<T*>(p->eps_ws);
   }
-  if (p->scheme == FE_CONJUGATE_GRADIENT) return solve_cg<T>(p, phase, cT, c64, coef, g, macro, eps, tol, out);
+  if (p->scheme == FE_CONJUGATE_GRADIENT)
+    return p->displacement ? solve_cg<T>(p, phase, cT, c64, coef, g, macro, eps, tol, out)
+                           : solve_cg6<T>(p, phase, coef, g, ref, macro, eps, tol, out);
   if (strain_init) {
     if (strain_init != eps)
       HIP_TRY(hipMemcpyAsync(eps, strain_init, 6 * (size_t)N * sizeof(T), hipMemcpyDeviceToDevice, s));
@@ -776,7 +912,9 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
   const int max_iter = p->opt.max_iter;
   const int every = p->opt.check_every;
 
-  const bool can_refine = p->opt.refine && sizeof(T) == 4 && p->displacement;
+  const bool can_refine = p->opt.refine && sizeof(T) == 4;
+  GreenConst<T> gz = g;  // the correction of an anchored iteration: no applied strain (the residual field replaces it)
+  for (int i = 0; i < 6; ++i) gz.macro[i] = T(0);
   GreenConst<double> g64;
   g64.lam0 = ref.lam0;
   g64.mu0 = ref.mu0;
@@ -809,8 +947,54 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
     return FE_OK;
   };
 
+  // six-component form: the anchor's iterate e_hi = eps_bar - G' tau(eps)
+  // and its residual r = e_hi - eps, the mean and the divergence spectrum of
+  // sigma(eps), all from float64 arithmetic; the float32 iterations then
+  // solve for the correction delta with r in place of the applied strain
+  // (eqs. (9), (16) are affine in the iterate) and eta adds the anchor's
+  // divergence spectrum before the square.
+  auto reanchor6 = [&]() -> fe_status {
+    const size_t spec = (size_t)spec_size(d);
+    fe_status ss = six64_workspace(p);
+    if (ss != FE_OK) return ss;
+    if (!p->dlt) {
+      HIP_TRY(dmalloc(p, &p->dlt, 6 * (size_t)N * sizeof(T)));
+      HIP_TRY(dmalloc(p, &p->rfield, 6 * (size_t)N * sizeof(T)));
+      HIP_TRY(dmalloc(p, &p->dbase6, 6 * spec * sizeof(cpx<T>)));
+    }
+    if (anchored) Launch<T>::axpy(eps, it, 6 * N, s);
+    double* e64 = p->six64a;
+    double* w64 = p->six64b;
+    cpx<double>* S64 = p->six64s;
+    const Tables<double>& t = p->t64;
+    const WaveTables<double> wt64 = wave_tables<double>(p);
+    Launch<double>::convert_to(e64, eps, sizeof(T) == 8, 6 * N, s);
+    Launch<double>::tau6(e64, phase, p->coef64, w64, 0, nullptr, p->div_blocks, d, s);
+    Launch<double>::zr2c(w64, S64, 6, d, t.tw[2], s);
+    Launch<double>::yfft(S64, 6, d, t.tw[1], 0, s);
+    Launch<double>::xgreen6(S64, d, t.tw[0], wt64, g64, p->op, s);
+    Launch<double>::yfft(S64, 6, d, t.tw[1], 1, s);
+    Launch<double>::zc2r(S64, w64, 6, d, t.tw[2], s);
+    launch_residual6<T>(w64, eps, static_cast<T*>(p->rfield), d, s);
+    Launch<double>::tau6(e64, phase, p->coef64, w64, 1, p->partials, p->div_blocks, d, s);
+    launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
+    Launch<double>::zr2c(w64, S64, 6, d, t.tw[2], s);
+    Launch<double>::yfft(S64, 6, d, t.tw[1], 0, s);
+    launch_xeta6<double, T>(S64, d, t.tw[0], wt64, nullptr, p->op, XETA_STORE, static_cast<cpx<T>*>(p->dbase6), s);
+    HIP_TRY(hipMemsetAsync(p->dlt, 0, 6 * (size_t)N * sizeof(T), s));
+    HIP_TRY(hipMemcpyAsync(p->h_red, p->red, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < 6; ++i) mean_hi[i] = p->h_red[1 + i] / (double)N;
+    it = static_cast<T*>(p->dlt);
+    rf = static_cast<const T*>(p->rfield);
+    anchored = true;
+    ++refinements;
+    return FE_OK;
+  };
+
   // float64 re-anchor at the strain eps (+ it if anchored)
   auto reanchor = [&]() -> fe_status {
+    if (!p->displacement) return reanchor6();
     const size_t spec = (size_t)spec_size(d);
     {
       fe_status ss = sync_iterate();
@@ -903,11 +1087,13 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
       if (check) tm.run(FE_PASS_ETA, [&] { launch_reduce(p->partials, nb_D, 7, p->red, s); });
     } else if (check) {
       tm.run(FE_PASS_ETA, [&] {
-        Launch<T>::tau6(eps, phase, coef, R, 1, p->partials, p->div_blocks, d, s);
+        Launch<T>::tau6(it, phase, coef, R, 1, p->partials, p->div_blocks, d, s);
         launch_reduce(p->partials, p->div_blocks, 7, p->red, s);
         Launch<T>::zr2c(R, S, 6, d, tb.tw[2], s);
         Launch<T>::yfft(S, 6, d, tb.tw[1], 0, s);
-        const int xblk = Launch<T>::xeta6(S, d, tb.tw[0], wt, p->partials2, p->op, s);
+        const int xblk = anchored ? launch_xeta6<T, T>(S, d, tb.tw[0], wt, p->partials2, p->op, XETA_BASE,
+                                                       static_cast<cpx<T>*>(p->dbase6), s)
+                                  : Launch<T>::xeta6(S, d, tb.tw[0], wt, p->partials2, p->op, s);
         launch_reduce(p->partials2, xblk, 1, p->red + 8, s);
       });
     }
@@ -1045,13 +1231,13 @@ static fe_status solve_impl(fe_plan* p, const uint8_t* phase, const fe_materials
         have_D = true;
       }
     } else {
-      tm.run(FE_PASS_POINTWISE, [&] { Launch<T>::tau6(eps, phase, coef, R, 0, nullptr, p->div_blocks, d, s); });
+      tm.run(FE_PASS_POINTWISE, [&] { Launch<T>::tau6(it, phase, coef, R, 0, nullptr, p->div_blocks, d, s); });
       tm.run(FE_PASS_ZFWD, [&] { Launch<T>::zr2c(R, S, 6, d, tb.tw[2], s); });
       tm.run(FE_PASS_YFWD, [&] { Launch<T>::yfft(S, 6, d, tb.tw[1], 0, s); });
-      tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen6(S, d, tb.tw[0], wt, g, p->op, s); });
+      tm.run(FE_PASS_XGREEN, [&] { Launch<T>::xgreen6(S, d, tb.tw[0], wt, anchored ? gz : g, p->op, s); });
       tm.run(FE_PASS_YINV, [&] { Launch<T>::yfft(S, 6, d, tb.tw[1], 1, s); });
       tm.run(FE_PASS_ZINV, [&] { Launch<T>::zc2r(S, R, 6, d, tb.tw[2], s); });
-      tm.run(FE_PASS_UPDATE, [&] { Launch<T>::update6(R, eps, phase, coef, d, accel, s); });
+      tm.run(FE_PASS_UPDATE, [&] { Launch<T>::update6(R, it, phase, coef, d, accel, s, anchored ? rf : nullptr); });
     }
     HIP_TRY(hipGetLastError());
   }
@@ -1206,7 +1392,7 @@ extern "C" fe_status fe_solve_static(fe_grid g, fe_discretization disc, fe_schem
     o = *opt;
   }
   if (disc != FE_GREEN_WP && disc != FE_GREEN_ROT)
-    return fail(disc >= FE_GREEN_MS && disc <= FE_GREEN_CENTERED ? FE_ERR_UNSUPPORTED : FE_ERR_INVALID_ARG,
+    return fail(disc >= FE_GREEN_MS && disc <= FE_GREEN_MS_SYMMETRIZED ? FE_ERR_UNSUPPORTED : FE_ERR_INVALID_ARG,
                 "fe_solve_static runs the WP and ROT operators");
   if (scheme != FE_DIRECT && scheme != FE_ACCELERATED)
     return fail(scheme == FE_CONJUGATE_GRADIENT ? FE_ERR_UNSUPPORTED : FE_ERR_INVALID_ARG,
@@ -1617,7 +1803,9 @@ extern "C" fe_status fe_solve_batched(fe_discretization disc, fe_scheme scheme, 
                                       double* seconds) {
   if (!desc || !results) return fail(FE_ERR_INVALID_ARG, "desc or results is NULL");
   if (disc != FE_GREEN_WP && disc != FE_GREEN_ROT)
-    return fail(disc == FE_GREEN_MS || disc == FE_GREEN_CENTERED ? FE_ERR_UNSUPPORTED : FE_ERR_INVALID_ARG,
+    return fail(disc == FE_GREEN_MS || disc == FE_GREEN_CENTERED || disc == FE_GREEN_MS_SYMMETRIZED
+                    ? FE_ERR_UNSUPPORTED
+                    : FE_ERR_INVALID_ARG,
                 "batched solves support the WP and ROT operators");
   if (scheme == FE_CONJUGATE_GRADIENT)
     return fail(FE_ERR_UNSUPPORTED, "batched solves run the direct and accelerated schemes");

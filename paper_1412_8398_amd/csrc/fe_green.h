@@ -52,7 +52,7 @@ __device__ __forceinline__ void wave_k(const WaveTables<T>& wt, int mx, int my, 
     k[0] = mk(ax, bx);
     k[1] = mk(ay, by);
     k[2] = mk(az, bz);
-  } else if (OP == OP_MS || OP == OP_C) {  // i q or i sin q
+  } else if (OP == OP_MS || OP == OP_C || OP == OP_MSS) {  // i q or i sin q
     k[0] = mk(T(0), ax);
     k[1] = mk(T(0), ay);
     k[2] = mk(T(0), az);
@@ -106,11 +106,42 @@ __device__ __forceinline__ void green_disp(cpx<T> (&b)[3], const WaveTables<T>& 
   }
 }
 
+// eps/N = -sym(k (x) u)/N with u = -A^-1 conj(k).tau (eq. (19)), for |k| > 0.
+template <typename T>
+__device__ __forceinline__ void green_sym_solve(const cpx<T> (&k)[3], const cpx<T> (&tv)[6], const GreenConst<T>& g,
+                                                cpx<T> (&out)[6]) {
+  cpx<T> b[3], u[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    cpx<T> acc = mk(T(0), T(0));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc = add(acc, mul(conj(k[i]), tv[voigt_of(i, j)]));
+    b[j] = acc;
+  }
+  woodbury_solve(k, b, g.lam0, g.mu0, u);
+  const T f = -g.inv_n;
+  out[0] = scale(mul(k[0], u[0]), f);
+  out[1] = scale(mul(k[1], u[1]), f);
+  out[2] = scale(mul(k[2], u[2]), f);
+  out[3] = scale(add(mul(k[1], u[2]), mul(k[2], u[1])), T(0.5) * f);
+  out[4] = scale(add(mul(k[0], u[2]), mul(k[2], u[0])), T(0.5) * f);
+  out[5] = scale(add(mul(k[0], u[1]), mul(k[1], u[0])), T(0.5) * f);
+}
+
+// Nyquist flag of the MS wave tables at (mx, my, mz): some q_i = pi (even L_i)
+template <typename T>
+__device__ __forceinline__ bool nyquist_mode(const WaveTables<T>& wt, int mx, int my, int mz) {
+  return (wt.x[2 * mx + 1] != T(0)) || (wt.y[2 * my + 1] != T(0)) || (wt.z[2 * mz + 1] != T(0));
+}
+
 // Six-component form (any operator): tau(q) -> eps(q)/N.
 //   q = 0: eps_bar (eq. (6));  MS with some q_i = pi: -(C0)^-1 tau (eq. (14));
 //   ordinary: b_j = conj(k_i) tau_ij, u = -A^-1 b, eps = sym(k (x) u) (eq. (19));
 //   ROT with two q_i = pi: |k| = 0, eps = 0 (eq. (41));
-//   C with every q_i in {0, pi}: |k| = 0, eps = 0 (eq. (29)).
+//   C with every q_i in {0, pi}: |k| = 0, eps = 0 (eq. (29));
+//   MSS with some q_i = pi: the mean of the ordinary formula at k = i q and at
+//   k' = i q', q' = -q with the Nyquist components kept at +pi (the grid
+//   partner of q; eq. (15)).
 template <typename T, int OP>
 __device__ __forceinline__ void green_six(cpx<T> (&tv)[6], const WaveTables<T>& wt, int mx, int my, int mz,
                                           const GreenConst<T>& g) {
@@ -119,8 +150,21 @@ __device__ __forceinline__ void green_six(cpx<T> (&tv)[6], const WaveTables<T>& 
     for (int c = 0; c < 6; ++c) tv[c] = mk(g.macro[c], T(0));
     return;
   }
+  if (OP == OP_MSS && nyquist_mode(wt, mx, my, mz)) {
+    const T qx = wt.x[2 * mx], qy = wt.y[2 * my], qz = wt.z[2 * mz];
+    const cpx<T> k[3] = {mk(T(0), qx), mk(T(0), qy), mk(T(0), qz)};
+    const cpx<T> kp[3] = {mk(T(0), wt.x[2 * mx + 1] != T(0) ? qx : -qx),
+                          mk(T(0), wt.y[2 * my + 1] != T(0) ? qy : -qy),
+                          mk(T(0), wt.z[2 * mz + 1] != T(0) ? qz : -qz)};
+    cpx<T> e1[6], e2[6];
+    green_sym_solve(k, tv, g, e1);
+    green_sym_solve(kp, tv, g, e2);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tv[c] = scale(add(e1[c], e2[c]), T(0.5));
+    return;
+  }
   if (OP == OP_MS) {
-    const bool nyq = (wt.x[2 * mx + 1] != T(0)) || (wt.y[2 * my + 1] != T(0)) || (wt.z[2 * mz + 1] != T(0));
+    const bool nyq = nyquist_mode(wt, mx, my, mz);
     if (nyq) {
       const cpx<T> tr = add(add(tv[0], tv[1]), tv[2]);
 #pragma unroll
@@ -138,30 +182,50 @@ __device__ __forceinline__ void green_six(cpx<T> (&tv)[6], const WaveTables<T>& 
     for (int c = 0; c < 6; ++c) tv[c] = mk(T(0), T(0));
     return;
   }
-  cpx<T> b[3], u[3];
+  cpx<T> e[6];
+  green_sym_solve(k, tv, g, e);
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    cpx<T> acc = mk(T(0), T(0));
-#pragma unroll
-    for (int i = 0; i < 3; ++i) acc = add(acc, mul(conj(k[i]), tv[voigt_of(i, j)]));
-    b[j] = acc;
-  }
-  woodbury_solve(k, b, g.lam0, g.mu0, u);
-  const T f = -g.inv_n;
-  tv[0] = scale(mul(k[0], u[0]), f);
-  tv[1] = scale(mul(k[1], u[1]), f);
-  tv[2] = scale(mul(k[2], u[2]), f);
-  tv[3] = scale(add(mul(k[1], u[2]), mul(k[2], u[1])), T(0.5) * f);
-  tv[4] = scale(add(mul(k[0], u[2]), mul(k[2], u[0])), T(0.5) * f);
-  tv[5] = scale(add(mul(k[0], u[1]), mul(k[1], u[0])), T(0.5) * f);
+  for (int c = 0; c < 6; ++c) tv[c] = e[c];
 }
 
 // |conj(k).sigma(q)|^2 summed over the stored q and, for 0 < mz < nz/2, its
 // mirror -q (coefficient conj sigma(q), wave vector read at the mirror
 // indices) -- eq. (43) over the full spectrum from a half spectrum.
+// The two divergence vectors behind eta_six: conj(k(q)).sigma(q) into a[0..2]
+// and, where the half spectrum stands for the mirror -q too (0 < mz < nz/2),
+// conj(k(-q)).conj(sigma(q)) into b[0..2] (else b = 0).  Returns whether b
+// is used.
+template <typename T, int OP>
+__device__ __forceinline__ bool div_six(const cpx<T> (&sv)[6], const WaveTables<T>& wt, int mx, int my, int mz,
+                                        const Dims& d, cpx<T> (&a)[3], cpx<T> (&b)[3]) {
+  cpx<T> k[3];
+  wave_k<T, OP>(wt, mx, my, mz, k);
+  const bool off = OP == OP_MSS && nyquist_mode(wt, mx, my, mz);  // as eta_six
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    a[j] = mk(T(0), T(0));
+    if (!off) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) a[j] = add(a[j], mul(conj(k[i]), sv[voigt_of(i, j)]));
+    }
+    b[j] = mk(T(0), T(0));
+  }
+  if (off || !(mz > 0 && 2 * mz < d.nz)) return false;
+  const int qx = mx == 0 ? 0 : d.nx - mx, qy = my == 0 ? 0 : d.ny - my, qz = d.nz - mz;
+  wave_k<T, OP>(wt, qx, qy, qz, k);
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) b[j] = add(b[j], mul(conj(k[i]), conj(sv[voigt_of(i, j)])));
+  return true;
+}
+
 template <typename T, int OP>
 __device__ __forceinline__ double eta_six(const cpx<T> (&sv)[6], const WaveTables<T>& wt, int mx, int my, int mz,
                                           const Dims& d) {
+  // MSS imposes equilibrium off the Nyquist modes only (a mode and its
+  // mirror are Nyquist together): eq. (43) sums over the others
+  if (OP == OP_MSS && nyquist_mode(wt, mx, my, mz)) return 0.0;
   cpx<T> k[3];
   wave_k<T, OP>(wt, mx, my, mz, k);
   double s = 0.0;

@@ -8,7 +8,9 @@
 
 namespace fe {
 
-enum Op { OP_MS = 0, OP_WP = 1, OP_ROT = 2, OP_C = 3 };
+// OP_MSS: the continuous operator with eq. (15)'s symmetrised Nyquist rule
+// in place of eq. (14)'s (C0)^-1
+enum Op { OP_MS = 0, OP_WP = 1, OP_ROT = 2, OP_C = 3, OP_MSS = 4 };
 
 struct Dims {
   int nx, ny, nz, H;  // H = nz/2 + 1 (half spectrum along z)
@@ -120,6 +122,15 @@ struct Launch {
   static int dot(const T* a, const T* b, long long n, double* partials, hipStream_t s);
   static int cg_step(T* v, const T* p, T* r, const T* Q, long long n, double* cgs, double* partials, hipStream_t s);
   static void cg_dir(T* p, const T* z, long long n, const double* cgs, int first, hipStream_t s);
+  // Six-component conjugate gradients (inner product sum a:C0:b, see
+  // k_cg6_step): Q = (negate ? -1 : 1) Rb taken out of the z-blocked layout,
+  // with the partial sums of <x, Q> (x nullable: <Q, Q>); the step
+  // eps += alpha p, r -= alpha Q with the partial sums of <r, r>.  Both
+  // return the number of partial sums (one double each).
+  static int cg6_take(const T* Rb, T* Q, const T* x, int negate, Dims d, double lam0, double mu0, double* partials,
+                      hipStream_t s);
+  static int cg6_step(T* eps, const T* p, T* r, const T* Q, long long N, double lam0, double mu0, double* cgs,
+                      double* partials, hipStream_t s);
   static void xgreen3(cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> wt, GreenConst<T> g, int op,
                       hipStream_t s, Batch bt = Batch{nullptr, 0}, const GreenConst<T>* gs = nullptr, int nsamp = 1);
 
@@ -131,8 +142,10 @@ struct Launch {
   // Returns the number of partial sums written.
   static int xeta6(const cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> wt, double* partials, int op,
                    hipStream_t s);
+  // e (the inverse transform output) plus rfield (nullable, plain [6][N]:
+  // the anchor's strain residual replacing the applied strain) updates eps
   static void update6(const T* e, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, Dims d,
-                      int accelerated, hipStream_t s);
+                      int accelerated, hipStream_t s, const T* rfield = nullptr);
 
   // Strided FFT passes.
   static void zr2c(const T* R, cpx<T>* S, int ncomp, Dims d, const cpx<T>* twz, hipStream_t s,
@@ -145,6 +158,21 @@ struct Launch {
   static void stress(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* sigma, long long N,
                      hipStream_t s);
 };
+
+enum { XETA_PLAIN = 0, XETA_BASE = 1, XETA_STORE = 2 };
+// Spectral eta of the six-component form (mode XETA_PLAIN, XETA_BASE,
+// XETA_STORE of fe_passes.h; base: the anchor's divergence spectrum, 6 half
+// spectra of TS, read by XETA_BASE and written by XETA_STORE; these two
+// modes take OP_MS or OP_C).  Returns the number of partial sums written.
+template <typename T, typename TS>
+int launch_xeta6(const cpx<T>* S, Dims d, const cpx<T>* twx, WaveTables<T> wt, double* partials, int op, int mode,
+                 cpx<TS>* base, hipStream_t s);
+
+// r = e_hi - eps (r and eps plain [6][N] of TE, e_hi the float64 inverse
+// transform output in the z-blocked layout): the six-component anchor's
+// strain residual.
+template <typename TE>
+void launch_residual6(const double* e_hi, const TE* eps, TE* r, Dims d, hipStream_t s);
 
 // Conjugate gradients: |r|^2 and the sums of sigma taken from the last fused
 // gradient/divergence launch's reduced sums (cgs[16..22]).

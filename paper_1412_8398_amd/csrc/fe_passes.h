@@ -291,10 +291,22 @@ __global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xgreen6(cpx<T>* __re
   }
 }
 
-template <typename T, int N, int OP>
+// Spectral equilibrium norm (eq. (43)) of a stress whose z and y transforms
+// are in S: forward x transform, then per frequency the divergence.
+//   XETA_PLAIN  partial sums of |conj(k).sigma|^2 over q and its mirror;
+//   XETA_BASE   the same with a stored divergence spectrum added before the
+//               square (the anchor's stress, a = div sigma(delta) + A,
+//               b = div of the mirror + B): eta of anchor + correction
+//               without forming their sum in float32;
+//   XETA_STORE  writes A and B (rounded to TS) instead of reducing.
+// A and B are complex [3][Hp ny lines][nx], the spectrum's line layout
+// (modes XETA_* in fe_kernels.h).
+
+template <typename T, int N, int OP, int MODE, typename TS>
 __global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xeta6(const cpx<T>* __restrict__ S, Dims d,
                                                                 const cpx<T>* __restrict__ tw, WaveTables<T> wt,
-                                                                double* __restrict__ partials) {
+                                                                double* __restrict__ partials,
+                                                                cpx<TS>* __restrict__ base) {
   using C = LineCfg<T, N, 6>;
   __shared__ cpx<T> lds[C::LPB * C::LINE];
   __shared__ double red[16];
@@ -304,14 +316,16 @@ __global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xeta6(const cpx<T>* 
   int mz, my;
   const bool ok = xline_of(d, line, mz, my);
   const long long cs = (long long)nlines * N;
-  const cpx<T>* base = S + (long long)(ok ? line : 0) * N + t;
+  const cpx<T>* src = S + (long long)(ok ? line : 0) * N + t;
   cpx<T> v[6][C::E];
 #pragma unroll
   for (int c = 0; c < 6; ++c)
 #pragma unroll
-    for (int m = 0; m < C::E; ++m) v[c][m] = ok ? base[c * cs + m * C::P] : mk(T(0), T(0));
+    for (int m = 0; m < C::E; ++m) v[c][m] = ok ? src[c * cs + m * C::P] : mk(T(0), T(0));
   const auto at = [l](int, int pos) { return l * C::LINE + pad16(pos); };
   fft_regs<T, N, C::E, 6, false, true>(v, t, lds, at, tw);
+  const long long bs = 3 * cs;  // B follows A
+  cpx<TS>* bl = base + (long long)(ok ? line : 0) * N + t;
   double acc[1] = {0.0};
   if (ok) {
 #pragma unroll
@@ -319,9 +333,33 @@ __global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xeta6(const cpx<T>* 
       cpx<T> sv[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) sv[c] = v[c][m];
-      acc[0] += eta_six<T, OP>(sv, wt, t + m * C::P, my, mz, d);
+      if (MODE == XETA_PLAIN) {
+        acc[0] += eta_six<T, OP>(sv, wt, t + m * C::P, my, mz, d);
+      } else {
+        cpx<T> a[3], b[3];
+        const bool mirror = div_six<T, OP>(sv, wt, t + m * C::P, my, mz, d, a, b);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          cpx<TS>* pa = bl + j * cs + m * C::P;
+          cpx<TS>* pb = bl + bs + j * cs + m * C::P;
+          if (MODE == XETA_STORE) {
+            *pa = mk(TS(a[j].re), TS(a[j].im));
+            *pb = mk(TS(b[j].re), TS(b[j].im));
+          } else {
+            const cpx<TS> A = *pa;
+            const double ar = double(a[j].re) + double(A.re), ai = double(a[j].im) + double(A.im);
+            acc[0] += ar * ar + ai * ai;
+            if (mirror) {
+              const cpx<TS> B = *pb;
+              const double br = double(b[j].re) + double(B.re), bi = double(b[j].im) + double(B.im);
+              acc[0] += br * br + bi * bi;
+            }
+          }
+        }
+      }
     }
   }
+  if (MODE == XETA_STORE) return;
   block_sum<1>(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
 }

@@ -694,6 +694,67 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ v, const T* __r
   }
 }
 
+// Conjugate gradients in the six-component form (strain iterate, inner
+// product <a, b> = sum_x a : C0 : b with a : C0 : b = lam0 tr a tr b
+// + 2 mu0 (sum_i a_ii b_ii + 2 sum_{i<j} a_ij b_ij), tensor Voigt planes).
+template <typename T>
+__device__ __forceinline__ double c0_dot(const double* a, const double* b, double lam0, double mu0) {
+  return lam0 * (a[0] + a[1] + a[2]) * (b[0] + b[1] + b[2]) +
+         2.0 * mu0 * (a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + 2.0 * (a[3] * b[3] + a[4] * b[4] + a[5] * b[5]));
+}
+
+// Q = sgn * Rb (Rb: the inverse transform output, z-blocked; Q plain) and the
+// partial sums of <x, Q> (x nullable: then <Q, Q>).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg6_take(const T* __restrict__ Rb, T* __restrict__ Q, const T* __restrict__ x,
+                                                  T sgn, Dims d, double lam0, double mu0,
+                                                  double* __restrict__ partials) {
+  __shared__ double red[16];
+  const long long N = d.N;
+  double acc[1] = {0.0};
+  for (long long v = blockIdx.x * 256LL + threadIdx.x; v < N; v += (long long)gridDim.x * 256) {
+    const long long vb = zblk(d, v);
+    double q[6], a[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const T qk = sgn * Rb[k * N + vb];
+      Q[k * N + v] = qk;
+      q[k] = double(qk);
+      a[k] = x ? double(x[k * N + v]) : q[k];
+    }
+    acc[0] += c0_dot<T>(a, q, lam0, mu0);
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+}
+
+// alpha = <r, r> / <p, Q> (cgs[0], cgs[16]); eps += alpha p; r -= alpha Q;
+// partial sums of <r, r>.  Block 0 moves <r, r> to the previous slot cgs[1].
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg6_step(T* __restrict__ eps, const T* __restrict__ p, T* __restrict__ r,
+                                                  const T* __restrict__ Q, long long N, double lam0, double mu0,
+                                                  double* __restrict__ cgs, double* __restrict__ partials) {
+  __shared__ double red[16];
+  const T a = T(cgs[0] / cgs[16]);
+  double acc[1] = {0.0};
+  for (long long v = blockIdx.x * 256LL + threadIdx.x; v < N; v += (long long)gridDim.x * 256) {
+    double rr[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      eps[k * N + v] += a * p[k * N + v];
+      const T rk = r[k * N + v] - a * Q[k * N + v];
+      r[k * N + v] = rk;
+      rr[k] = double(rk);
+    }
+    acc[0] += c0_dot<T>(rr, rr, lam0, mu0);
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = acc[0];
+    if (blockIdx.x == 0) cgs[1] = cgs[0];
+  }
+}
+
 // p = z + beta p, beta = rho / previous rho (p = z when first)
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_dir(T* __restrict__ p, const T* __restrict__ z, long long n,
@@ -745,10 +806,11 @@ __global__ __launch_bounds__(256) void k_tau6(const T* __restrict__ eps, const u
   }
 }
 
-template <typename T, bool AS>
+template <typename T, bool AS, bool RF>
 __global__ __launch_bounds__(256) void k_update6(const T* __restrict__ e, T* __restrict__ eps,
                                                  const uint8_t* __restrict__ phase,
-                                                 const PhaseCoef<T>* __restrict__ coef, Dims d) {
+                                                 const PhaseCoef<T>* __restrict__ coef, Dims d,
+                                                 const T* __restrict__ rf) {
   const long long N = d.N;
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
     const long long vb = zblk(d, v);  // e: the inverse transform output, z-blocked
@@ -758,7 +820,7 @@ __global__ __launch_bounds__(256) void k_update6(const T* __restrict__ e, T* __r
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         cur[k] = eps[k * N + v];
-        dd[k] = e[k * N + vb] - cur[k];
+        dd[k] = (RF ? e[k * N + vb] + rf[k * N + v] : e[k * N + vb]) - cur[k];
       }
       const T sph = (dd[0] + dd[1] + dd[2]) * T(1.0 / 3.0);
 #pragma unroll
@@ -767,8 +829,19 @@ __global__ __launch_bounds__(256) void k_update6(const T* __restrict__ e, T* __r
       for (int k = 3; k < 6; ++k) eps[k * N + v] = cur[k] + pc.am * dd[k];
     } else {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) eps[k * N + v] = e[k * N + vb];
+      for (int k = 0; k < 6; ++k) eps[k * N + v] = RF ? e[k * N + vb] + rf[k * N + v] : e[k * N + vb];
     }
+  }
+}
+
+template <typename TE>
+__global__ __launch_bounds__(256) void k_residual6(const double* __restrict__ e_hi, const TE* __restrict__ eps,
+                                                   TE* __restrict__ r, Dims d) {
+  const long long N = d.N;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N; v += (long long)gridDim.x * blockDim.x) {
+    const long long vb = zblk(d, v);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r[k * N + v] = TE(e_hi[k * N + vb] - double(eps[k * N + v]));
   }
 }
 
@@ -934,6 +1007,21 @@ void Launch<T>::cg_dir(T* p, const T* z, long long n, const double* cgs, int fir
 void launch_cg_restart(double* cgs, hipStream_t s) { hipLaunchKernelGGL(k_cg_restart, dim3(1), dim3(64), 0, s, cgs); }
 
 template <typename T>
+int Launch<T>::cg6_take(const T* Rb, T* Q, const T* x, int negate, Dims d, double lam0, double mu0, double* partials,
+                        hipStream_t s) {
+  hipLaunchKernelGGL((k_cg6_take<T>), dim3(kCgBlocks), dim3(256), 0, s, Rb, Q, x, negate ? T(-1) : T(1), d, lam0, mu0,
+                     partials);
+  return kCgBlocks;
+}
+
+template <typename T>
+int Launch<T>::cg6_step(T* eps, const T* p, T* r, const T* Q, long long N, double lam0, double mu0, double* cgs,
+                        double* partials, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg6_step<T>), dim3(kCgBlocks), dim3(256), 0, s, eps, p, r, Q, N, lam0, mu0, cgs, partials);
+  return kCgBlocks;
+}
+
+template <typename T>
 void Launch<T>::tau6(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, T* out, int write_sigma,
                      double* partials, int nblocks, Dims d, hipStream_t s) {
   hipLaunchKernelGGL((k_tau6<T>), dim3(nblocks), dim3(kThreads), 0, s, eps, phase, coef, out, write_sigma, partials,
@@ -942,13 +1030,24 @@ void Launch<T>::tau6(const T* eps, const uint8_t* phase, const PhaseCoef<T>* coe
 
 template <typename T>
 void Launch<T>::update6(const T* e, T* eps, const uint8_t* phase, const PhaseCoef<T>* coef, Dims d, int accelerated,
-                        hipStream_t s) {
-  if (accelerated)
-    hipLaunchKernelGGL((k_update6<T, true>), dim3(grid_for(d.N, 1 << 20)), dim3(kThreads), 0, s, e, eps, phase, coef,
-                       d);
-  else
-    hipLaunchKernelGGL((k_update6<T, false>), dim3(grid_for(d.N, 1 << 20)), dim3(kThreads), 0, s, e, eps, phase,
-                       coef, d);
+                        hipStream_t s, const T* rfield) {
+  const dim3 grid(grid_for(d.N, 1 << 20)), block(kThreads);
+  if (accelerated) {
+    if (rfield)
+      hipLaunchKernelGGL((k_update6<T, true, true>), grid, block, 0, s, e, eps, phase, coef, d, rfield);
+    else
+      hipLaunchKernelGGL((k_update6<T, true, false>), grid, block, 0, s, e, eps, phase, coef, d, rfield);
+  } else {
+    if (rfield)
+      hipLaunchKernelGGL((k_update6<T, false, true>), grid, block, 0, s, e, eps, phase, coef, d, rfield);
+    else
+      hipLaunchKernelGGL((k_update6<T, false, false>), grid, block, 0, s, e, eps, phase, coef, d, rfield);
+  }
+}
+
+template <typename TE>
+void launch_residual6(const double* e_hi, const TE* eps, TE* r, Dims d, hipStream_t s) {
+  hipLaunchKernelGGL((k_residual6<TE>), dim3(grid_for(d.N, 1 << 20)), dim3(kThreads), 0, s, e_hi, eps, r, d);
 }
 
 template <typename T>
@@ -972,12 +1071,16 @@ void launch_reduce(const double* partials, int nblocks, int nv, double* out, hip
   template int Launch<T>::dot(const T*, const T*, long long, double*, hipStream_t);                        \
   template int Launch<T>::cg_step(T*, const T*, T*, const T*, long long, double*, double*, hipStream_t);    \
   template void Launch<T>::cg_dir(T*, const T*, long long, const double*, int, hipStream_t);               \
+  template int Launch<T>::cg6_take(const T*, T*, const T*, int, Dims, double, double, double*, hipStream_t); \
+  template int Launch<T>::cg6_step(T*, const T*, T*, const T*, long long, double, double, double*, double*,  \
+                                   hipStream_t);                                                              \
   template int Launch<T>::update_div(const T*, const T*, T*, const uint8_t*, const PhaseCoef<T>*, GreenConst<T>, \
                                      const T*, T*, const T*, double*, Dims, int, int, hipStream_t, Batch,         \
                                      const GreenConst<T>*, int);                                                  \
   template void Launch<T>::tau6(const T*, const uint8_t*, const PhaseCoef<T>*, T*, int, double*, int, Dims, \
                                 hipStream_t);                                                             \
-  template void Launch<T>::update6(const T*, T*, const uint8_t*, const PhaseCoef<T>*, Dims, int, hipStream_t); \
+  template void Launch<T>::update6(const T*, T*, const uint8_t*, const PhaseCoef<T>*, Dims, int, hipStream_t,   \
+                                   const T*);                                                                  \
   template void Launch<T>::stress(const T*, const uint8_t*, const PhaseCoef<T>*, T*, long long, hipStream_t);
 FE_INSTANTIATE(float)
 FE_INSTANTIATE(double)
@@ -990,6 +1093,8 @@ template int launch_div64<float>(const float*, const uint8_t*, const PhaseCoef<d
                                  Dims, int, hipStream_t, Batch, int);
 template int launch_div64<double>(const double*, const uint8_t*, const PhaseCoef<double>*, double*, double*, double*,
                                   Dims, int, hipStream_t, Batch, int);
+template void launch_residual6<float>(const double*, const float*, float*, Dims, hipStream_t);
+template void launch_residual6<double>(const double*, const double*, double*, Dims, hipStream_t);
 template void launch_residual<float>(const double*, const float*, GreenConst<double>, float*, Dims, int, hipStream_t);
 template void launch_residual<double>(const double*, const double*, GreenConst<double>, double*, Dims, int,
                                       hipStream_t);

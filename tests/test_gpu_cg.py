@@ -1,4 +1,5 @@
-"""Conjugate gradients on the GPU (FE_CONJUGATE_GRADIENT, WP and ROT): the
+"""Conjugate gradients on the GPU (FE_CONJUGATE_GRADIENT: WP and ROT on the
+corner displacement, MS and centered on the six-component strain): the
 iterates equal the oracle's conjugate gradients at equal iteration index
 (float64: strain to 1e-10 relative L2, eta^k to 1e-9 relative of eta^0 -- a
 recursive residual in another summation order carries rounding that the
@@ -43,7 +44,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("op", ["W", "R"])
+@pytest.mark.parametrize("op", ["W", "R", "MS", "C"])
 @pytest.mark.parametrize("shape", [(8, 12, 16), (12, 24, 256)])
 def test_cg_iterates_match_the_oracle_fp64(op, shape):
     """Equal iterates at k = 10 on a small cell and on one spanning several
@@ -60,7 +61,7 @@ def test_cg_iterates_match_the_oracle_fp64(op, shape):
     assert np.allclose(res.mean_stress, O.tensor_to_voigt(ref.mean_stress), rtol=1e-10, atol=1e-12)
 
 
-@pytest.mark.parametrize("op", ["W", "R"])
+@pytest.mark.parametrize("op", ["W", "R", "MS", "C"])
 def test_cg_converges_with_the_oracle_and_to_the_accelerated_solution(op):
     shape = (16, 16, 16)
     phase, E, nu = _three_phase(shape, seed=3)
@@ -98,12 +99,22 @@ def test_cg_fp32_reaches_tolerance_with_fp64_verification():
     assert tiny.status == fe.FE_NOT_CONVERGED and tiny.eta_verify_fp64 > 1e-11
 
 
+def test_cg_six_component_fp32():
+    """Float32 conjugate gradients in the six-component form (no refinement)
+    reach 1e-5 with the float64 verification agreeing, and the float64
+    solution's mean stress."""
+    phase, E, nu = _three_phase((32, 32, 32), seed=5)
+    ref, _ = _cg(phase, E, nu, "MS", "fp64", 2000, 1e-10)
+    res, _ = _cg(phase, E, nu, "MS", "fp32", 2000, 1e-5)
+    assert res.status == fe.FE_OK and res.eta_verify_fp64 <= 1.2e-5
+    assert np.allclose(res.mean_stress, ref.mean_stress, rtol=1e-4, atol=1e-5)
+
+
 def test_cg_error_paths():
     phase, E, nu = _three_phase((8, 8, 8))
-    for op in ("MS", "C"):
-        with pytest.raises(fe.FeError) as ei:
-            fe.Plan(8, green=op, scheme="CG", precision="fp64")
-        assert ei.value.status == fe.FE_ERR_UNSUPPORTED
+    with pytest.raises(fe.FeError) as ei:
+        fe.Plan(8, green="MSS", scheme="CG", precision="fp64")
+    assert ei.value.status == fe.FE_ERR_UNSUPPORTED
     with fe.Plan(8, green="R", scheme="CG", precision="fp64") as plan:
         init = torch.zeros((6, 8, 8, 8), dtype=torch.float64, device="cuda")
         with pytest.raises(fe.FeError) as ei:

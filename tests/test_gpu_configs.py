@@ -4,15 +4,18 @@ cannot run (256^3 and above): properties that hold at any size.
 * 256^3 Boolean spheres (radius 8, f = 0.3), matrix E = 1.5, nu = 0.25 (the
   paper's units), macroscopic shear eps_12 = 1:
   - contrast 100: the accelerated scheme with the MS, WP and rotated
-    operators converges; the effective shear modulus lies between the Reuss
-    and Voigt bounds; the three discretizations agree to a few percent (they
-    differ by discretization error only); float32 fields with float64
-    re-anchoring agree with float64 fields to 1e-5; the direct scheme reaches
-    the same mean stress (DS and AS share the fixed point).
-  - contrast 1e-6 (near-porous), accelerated rotated scheme with the explicit
-    reference medium E0 = 0.12 + sqrt(chi) in units of the matrix modulus 1.5,
-    nu0 = 0.25: slow; after 3000 iterations eta < 1e-5 in float64, float32
-    with re-anchoring reaches the same mean stress, 0 < mu_eff < Voigt.
+    operators converges in float32 with float64 re-anchoring (both the
+    displacement and the six-component form) to 1e-6 verified in float64;
+    the effective shear modulus lies between the Reuss and Voigt bounds; the
+    three discretizations agree to a few percent (they differ by
+    discretization error only); float32 agrees with float64 fields to 1e-5;
+    the direct scheme reaches the same mean stress (DS and AS share the
+    fixed point).
+  - contrast 1e-6 (near-porous): conjugate gradients with the rotated
+    operator reach 1e-6 in float64 and in float32 (float64 refinement), with
+    the same mean stress, 0 < mu_eff < Voigt; the accelerated scheme with
+    the section's optimised medium (E0 = 0.12 + sqrt(chi) in units of the
+    matrix modulus 1.5, nu0 = 0.25) is slower and is run to a cap.
 * 256^3 three-phase Voronoi (64 cells, the cell density of 4096 cells in
   1024^3): the 6x6 effective stiffness from six unit loads is symmetric,
   positive definite and between the Reuss and Voigt bounds (quadratic-form
@@ -55,9 +58,8 @@ def test_config2_contrast_100(boolean256):
     mu_v, mu_r = (1 - f) * mu[0] + f * mu[1], 1.0 / ((1 - f) / mu[0] + f / mu[1])
     res = {}
     for g in ("MS", "W", "R"):
-        # float32 MS (six-component form) has no float64 re-anchoring: float64 fields
-        r = _solve(phase, E, nu, g, "AS", "fp64" if g == "MS" else "fp32", 1e-6)
-        assert r.status == fe.FE_OK and r.eta_verify_fp64 <= 1.2e-6
+        r = _solve(phase, E, nu, g, "AS", "fp32", 1e-6)
+        assert r.status == fe.FE_OK and r.eta_verify_fp64 <= 1e-6
         res[g] = r.mean_stress[5] / 2.0
         assert mu_r <= res[g] <= mu_v
     vals = np.array(list(res.values()))
@@ -71,23 +73,27 @@ def test_config2_contrast_100(boolean256):
 
 
 def test_config2_near_porous(boolean256):
-    """Slow convergence at chi = 1e-6 (the paper's porous iteration counts
-    are not reproduced on this medium): after 3000 iterations the float64
-    run is below 1e-5, the float32 run with float64 re-anchoring reaches the
-    same mean stress, and the shear modulus is positive and below Voigt."""
+    """chi = 1e-6: conjugate gradients (rotated operator, eq. (17) medium)
+    converge to 1e-6 in float64 and in float32 with float64 refinement; the
+    two mean stresses agree (the problem is ill-conditioned near the porous
+    limit: eta = 1e-6 leaves about 1e-4 in the mean stress) and the shear
+    modulus is positive and below Voigt; the accelerated scheme with the
+    optimised medium gets within 1e-5 in 3000 iterations."""
     phase, f = boolean256
     chi = 1e-6
     E, nu = [1.5, 1.5 * chi], [0.25, 0.25]
-    E0 = 1.5 * (0.12 + math.sqrt(chi))
-    kw = dict(ref_rule="explicit", E0=E0, nu0=0.25)
-    r64 = _solve(phase, E, nu, "R", "AS", "fp64", 1e-6, max_iter=3000, **kw)
-    assert r64.status in (fe.FE_OK, fe.FE_NOT_CONVERGED) and r64.eta_verify_fp64 <= 1e-5
-    r32 = _solve(phase, E, nu, "R", "AS", "fp32", 1e-6, max_iter=3000, **kw)
-    assert r32.status in (fe.FE_OK, fe.FE_NOT_CONVERGED) and r32.eta_verify_fp64 <= 1e-5
-    assert abs(r32.mean_stress[5] - r64.mean_stress[5]) <= 1e-3 * abs(r64.mean_stress[5])
+    c64 = _solve(phase, E, nu, "R", "CG", "fp64", 1e-6, max_iter=3000)
+    assert c64.status == fe.FE_OK and c64.eta_verify_fp64 <= 1e-6
+    c32 = _solve(phase, E, nu, "R", "CG", "fp32", 1e-6, max_iter=3000)
+    assert c32.status == fe.FE_OK and c32.eta_verify_fp64 <= 1e-6
+    assert abs(c32.mean_stress[5] - c64.mean_stress[5]) <= 1e-3 * abs(c64.mean_stress[5])
     lam, mu = O.lame_from_young(E, nu)
-    mu_eff = r64.mean_stress[5] / 2.0
+    mu_eff = c64.mean_stress[5] / 2.0
     assert 0.0 < mu_eff < (1 - f) * mu[0] + f * mu[1]
+    E0 = 1.5 * (0.12 + math.sqrt(chi))
+    a64 = _solve(phase, E, nu, "R", "AS", "fp64", 1e-6, max_iter=3000, ref_rule="explicit", E0=E0, nu0=0.25)
+    assert a64.status in (fe.FE_OK, fe.FE_NOT_CONVERGED) and a64.eta_verify_fp64 <= 1e-5
+    assert abs(a64.mean_stress[5] - c64.mean_stress[5]) <= 1e-2 * abs(c64.mean_stress[5])
 
 
 def test_voronoi_256_effective_stiffness():

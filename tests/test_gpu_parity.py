@@ -73,7 +73,7 @@ def test_config1_direct_rotated_fp64_full_solve():
 
 
 @pytest.mark.parametrize("scheme", ["DS", "AS"])
-@pytest.mark.parametrize("op", ["MS", "W", "R", "C"])
+@pytest.mark.parametrize("op", ["MS", "W", "R", "C", "MSS"])
 def test_equal_iteration_parity_fp64(op, scheme):
     shape = (24, 16, 48)  # (nz, ny, nx): lengths 3*2^3, 2^4, 3*2^4
     phase, E, nu = _three_phase(shape)
@@ -86,7 +86,7 @@ def test_equal_iteration_parity_fp64(op, scheme):
 
 
 @pytest.mark.parametrize("scheme", ["DS", "AS"])
-@pytest.mark.parametrize("op", ["MS", "W", "R", "C"])
+@pytest.mark.parametrize("op", ["MS", "W", "R", "C", "MSS"])
 def test_equal_iteration_parity_fp32(op, scheme):
     shape = (24, 16, 48)
     phase, E, nu = _three_phase(shape)
@@ -129,7 +129,7 @@ def test_long_z_parity(shape):
 
 
 @pytest.mark.parametrize("scheme", ["DS", "AS"])
-@pytest.mark.parametrize("op", ["MS", "W", "R", "C"])
+@pytest.mark.parametrize("op", ["MS", "W", "R", "C", "MSS"])
 def test_one_plane_cells_parity_fp64(op, scheme):
     """nz = 1: the 2D problem in plane strain (every operator at q3 = 0),
     element by element against the oracle at equal iteration index."""
@@ -179,7 +179,7 @@ def test_homogeneous_medium_converges_in_one_step(op, rng):
     assert np.allclose(eps, np.array(MACRO)[:, None, None, None], atol=1e-13)
 
 
-@pytest.mark.parametrize("op,layers", [("R", [3, 9]), ("W", [5, 7]), ("MS", [4, 8])])
+@pytest.mark.parametrize("op,layers", [("R", [3, 9]), ("W", [5, 7]), ("MS", [4, 8]), ("MSS", [3, 5])])
 def test_laminate_exact_on_gpu(op, layers):
     labels = np.array([1] * layers[0] + [0] * layers[1], dtype=np.uint8)
     shape = (6, 8, sum(layers))

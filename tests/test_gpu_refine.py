@@ -32,22 +32,33 @@ def _solve(phase, E, nu, macro, op, scheme, precision, tol, max_iter, refine=Tru
     return r, eps.cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("op,scheme", [("R", "AS"), ("R", "DS"), ("W", "AS")])
+@pytest.mark.parametrize("op,scheme", [("R", "AS"), ("R", "DS"), ("W", "AS"), ("MS", "AS"), ("MS", "DS"), ("C", "AS"),
+                                       ("MSS", "AS")])
 def test_refinement_reaches_the_float64_solution(op, scheme):
+    """Displacement form (R, W): float64 displacement and divergences at each
+    anchor; six-component form (MS, C): the anchor's iterate, strain residual
+    and divergence spectrum in float64, the float32 iterations on the
+    correction."""
     phase, E, nu, macro = _case()
+    # the float32 storage floor of the returned strain is higher for the
+    # continuous and centered operators (their eta weighs the rounding noise
+    # of the stored strain with |k| up to pi sqrt(3) at the Nyquist corner,
+    # twice the rotated operator's): 1.05e-7 measured for MS-DS on this cell
+    tol = 1e-7 if op in ("R", "W") else 3e-7
     r64, e64 = _solve(phase, E, nu, macro, op, scheme, "fp64", 1e-11, 3000)
     assert r64.status == fe.FE_OK
-    r32, e32 = _solve(phase, E, nu, macro, op, scheme, "fp32", 1e-7, 3000)
+    r32, e32 = _solve(phase, E, nu, macro, op, scheme, "fp32", tol, 3000)
     assert r32.status == fe.FE_OK, (r32.status, r32.eta, r32.eta_verify_fp64)
     assert r32.refinements >= 1
-    assert r32.eta_verify_fp64 <= 1.2e-7
+    assert r32.eta_verify_fp64 <= 1.2 * tol
     assert np.linalg.norm(e32 - e64) / np.linalg.norm(e64) < 1e-5
     assert np.allclose(r32.mean_stress, r64.mean_stress, rtol=1e-6, atol=1e-8)
 
 
-def test_plain_float32_stalls_above_the_refined_tolerance():
+@pytest.mark.parametrize("op", ["R", "MS"])
+def test_plain_float32_stalls_above_the_refined_tolerance(op):
     phase, E, nu, macro = _case()
-    r, _ = _solve(phase, E, nu, macro, "R", "AS", "fp32", 1e-7, 400, refine=False)
+    r, _ = _solve(phase, E, nu, macro, op, "AS", "fp32", 1e-7, 400, refine=False)
     assert r.status == fe.FE_NOT_CONVERGED
     assert r.refinements == 0
     assert r.eta_verify_fp64 > 1e-7
