@@ -228,19 +228,30 @@ fe_status fe_effective_stiffness(fe_plan* plan, const uint8_t* phase, fe_materia
 /*
  * Batched solves of many independent microstructures (possibly of different
  * grid sizes) with one operator and scheme, e.g. to generate training data.
- * Samples are grouped by grid; each pass of an iteration is one launch over
- * all active samples of a group (the sample is the second grid dimension of
- * the launch), eta is reduced per sample on the device, and a sample retires
- * as soon as its own eta^k <= tol, its iteration cap is reached, or its eta
- * has not fallen by 5% over 100 iterations (the storage floor of float32
- * fields: FE_NOT_CONVERGED with the iterate reached at that point).
- * Supported: FE_GREEN_WP and FE_GREEN_ROT (displacement form); plain
- * iterations in the plan precision (no float64 re-anchoring).
+ * Supported: FE_GREEN_WP and FE_GREEN_ROT (displacement form), FE_DIRECT and
+ * FE_ACCELERATED.  Every sample follows the iteration of a single-sample
+ * fe_solve with refine = 0 (same kernels, constants and fixed-order
+ * reductions): a sample retires as soon as its own eta^k <= tol, its
+ * iteration cap is reached, eta rises for diverge_window checks
+ * (FE_DIVERGED), or eta has not fallen by 5% over 100 iterations (the
+ * float32 storage floor: FE_NOT_CONVERGED).
+ *   Float32 batches whose grid lengths are each one of 16, 24, 32, 48, 64,
+ *   96, 128 (at most 8 distinct grids) run as ONE cooperative persistent
+ *   launch: every pass of every iteration of all samples, with each sample's
+ *   eta, stop rules and retirement on the device.  Then the float64
+ *   verification; with opt->refine (the default) a sample whose float32
+ *   strain does not verify to tol continues with float64 fields from it
+ *   (one launch per pass per iteration over those samples only), its strain
+ *   is returned rounded to float32, verified again, and FE_OK only if that
+ *   verification meets tol; iterations counts both phases.
+ *   Other batches (float64, other lengths): one launch per pass per
+ *   iteration over the active samples of each grid, eta read back once per
+ *   iteration, no float64 continuation.
  *   desc->phase[i]   device, N_i uint8 labels of sample i
  *   desc->strain[i]  device, 6*N_i of the requested precision, receives eps of
  *                    sample i (NULL: not returned)
  *   results          host, n_samples entries
- *   seconds          host, may be NULL: device time of the iteration loops
+ *   seconds          host, may be NULL: device time of the iterations
  * Returns FE_OK if every sample converged, FE_NOT_CONVERGED / FE_DIVERGED if
  * some did not (see results[i].status), or an error (nothing written).
  */

@@ -373,9 +373,10 @@ class BatchSampleSpec:
     strain: object = None
 
 
-def _options(lib, precision, max_iter, ref_rule, ds_beta, E0, nu0, diverge_window, stream):
+def _options(lib, precision, max_iter, ref_rule, ds_beta, E0, nu0, diverge_window, stream, refine=True):
     opt = FePlanOptions()
     lib.fe_plan_options_default(C.byref(opt))
+    opt.refine = 1 if refine else 0
     opt.precision = PRECISION[precision]
     opt.max_iter = int(max_iter)
     opt.ref_rule = REF_RULE[ref_rule]
@@ -388,9 +389,11 @@ def _options(lib, precision, max_iter, ref_rule, ds_beta, E0, nu0, diverge_windo
 
 
 def solve_batched(samples, tol, green="R", scheme="AS", precision="fp32", max_iter=1000, ref_rule="paper",
-                  ds_beta=0.5, E0=0.0, nu0=0.25, diverge_window=50, stream=None, raise_on_error=True):
+                  ds_beta=0.5, E0=0.0, nu0=0.25, diverge_window=50, stream=None, raise_on_error=True, refine=True):
     """fe_solve_batched over a list of BatchSampleSpec; returns (results, status,
-    seconds) with one Result per sample (eta_history, pass timings empty)."""
+    seconds) with one Result per sample (eta_history, pass timings empty).
+    ``refine``: float32 samples whose strain does not verify to tol continue
+    in float64 (fe_plan_options.refine)."""
     lib = load_library()
     n = len(samples)
     if n == 0:
@@ -425,7 +428,7 @@ def solve_batched(samples, tol, green="R", scheme="AS", precision="fp32", max_it
         for q in range(6):
             macro[6 * i + q] = mv[q]
     desc = FeBatchDesc(n, grids, phases, mats, macro, strains)
-    opt = _options(lib, precision, max_iter, ref_rule, ds_beta, E0, nu0, diverge_window, stream)
+    opt = _options(lib, precision, max_iter, ref_rule, ds_beta, E0, nu0, diverge_window, stream, refine)
     res = (FeBatchResult * n)()
     sec = C.c_double(0.0)
     s = lib.fe_solve_batched(GREEN[green], SCHEME[scheme], C.byref(opt), C.byref(desc), float(tol), res,

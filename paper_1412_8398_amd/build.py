@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libfe.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["fe_pass_x6.hip", "fe_pass_e6.hip", "fe_pass_x3.hip", "fe_pass_z.hip", "fe_pass_y.hip", "fe_pointwise.hip", "fe_api.hip",
-           "fe_nn_conv.hip", "fe_nn_ops.hip", "fe_unet.hip", "fe_copy.hip"]
+           "fe_nn_conv.hip", "fe_nn_ops.hip", "fe_unet.hip", "fe_copy.hip", "fe_batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -16,6 +16,7 @@
 #include "fe_fft.h"
 #include "fe_error.h"
 #include "fe_kernels.h"
+#include "fe_batch.h"
 
 using namespace fe;
 
@@ -607,20 +608,35 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
     return FE_OK;
   };
 
-  HIP_TRY(hipEventRecord(p->ev0, s));
-  true_residual(r);
-  {
+  // r = D(v), z = K0^-1 r, p = z: the start, and every restart of the
+  // refined iteration below
+  auto start = [&]() -> fe_status {
+    true_residual(r);
     fe_status fs = fetch();
     if (fs != FE_OK) return fs;
+    HIP_TRY(hipEventRecord(p->evc, s));
+    precond();
+    Launch<T>::cg_dir(pd, z, n3, cgs, 1, s);
+    HIP_TRY(hipEventSynchronize(p->evc));
+    return FE_OK;
+  };
+  HIP_TRY(hipEventRecord(p->ev0, s));
+  {
+    fe_status fs = start();
+    if (fs != FE_OK) return fs;
   }
-  HIP_TRY(hipEventRecord(p->evc, s));
-  precond();
-  Launch<T>::cg_dir(pd, z, n3, cgs, 1, s);
-  HIP_TRY(hipEventSynchronize(p->evc));
   const int max_iter = p->opt.max_iter;
   fe_status status = FE_NOT_CONVERGED;
   double eta = eta_of(), restart_eta = INFINITY, best = INFINITY;
   int k = 0, best_k = 0;
+  // With refinement the float64 residual of v64 + v reaching target is not
+  // the end: the float32 strain returned carries its own rounding, which
+  // adds to that residual.  If the strain does not verify to tol, the
+  // iteration goes on towards half the target (at most four times, and only
+  // while the verified eta still falls by 10%).
+  double target = tol, ev = INFINITY, ev_last = INFINITY, eta_end = INFINITY;
+  float ms_elapsed = 0.f;
+  for (int lowered = 0;; ++lowered) {
   for (;; ++k) {
     record(k, eta);
     if (!std::isfinite(eta)) {
@@ -638,7 +654,7 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
     } else if (k - best_k >= 20) {
       stalled = true;
     }
-    if (eta <= tol || stalled) {
+    if (eta <= target || stalled) {
       const double eta_rec = eta;
       true_residual(Q);  // Q is free until the next step
       fe_status fs = fetch();
@@ -646,7 +662,7 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
       HIP_TRY(hipStreamSynchronize(s));
       eta = eta_of();
       record(k, eta);
-      if (eta <= tol) {
+      if (eta <= target) {
         status = FE_OK;
         break;
       }
@@ -694,22 +710,34 @@ static fe_status solve_cg(fe_plan* p, const uint8_t* phase, const std::vector<Ph
   }
   HIP_TRY(hipEventRecord(p->ev1, s));
   HIP_TRY(hipEventSynchronize(p->ev1));
-  const double eta_end = eta_of();
-  float ms_elapsed = 0.f;
+  eta_end = eta_of();
   HIP_TRY(hipEventElapsedTime(&ms_elapsed, p->ev0, p->ev1));
+  ev = eta_end;
+  if (sizeof(T) == 4) {
+    fe_status vs = verify_fp64<T>(p, eps, phase, &ev);
+    if (vs != FE_OK) return vs;
+  }
+  if (!(refine64 && status == FE_OK && !(ev <= tol))) break;
+  // the float32 strain returned must itself meet tol (its storage floor)
+  status = FE_NOT_CONVERGED;
+  if (lowered >= 4 || k >= max_iter || !(ev < 0.9 * ev_last)) break;
+  ev_last = ev;
+  target *= 0.5;
+  {
+    fe_status fs = start();  // r and z were overwritten by the strain above
+    if (fs != FE_OK) return fs;
+  }
+  eta = eta_of();
+  best = eta;
+  best_k = k;
+  restart_eta = INFINITY;
+  }
   for (int i = 0; i < 8; ++i) {
     out->pass_seconds[i] = 0.0;
     out->pass_launches[i] = 0;
   }
   out->refinements = 0;
   if (out->stress) Launch<T>::stress(eps, phase, coef, static_cast<T*>(out->stress), N, s);
-  double ev = eta_end;
-  if (sizeof(T) == 4) {
-    fe_status vs = verify_fp64<T>(p, eps, phase, &ev);
-    if (vs != FE_OK) return vs;
-    // the float32 strain returned must itself meet tol (its storage floor)
-    if (status == FE_OK && refine64 && !(ev <= tol)) status = FE_NOT_CONVERGED;
-  }
   HIP_TRY(hipStreamSynchronize(s));
   out->iterations = k;
   out->eta = status == FE_OK ? eta : eta_end;
@@ -1584,7 +1612,7 @@ fe_status alloc_class(BatchClass<T>& c, int op) {
 
 template <typename T>
 fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const fe_batch_desc* desc, double tol,
-                             fe_batch_result* results, double* seconds) {
+                             fe_batch_result* results, double* seconds, const float* const* init = nullptr) {
   hipStream_t s = (hipStream_t)o.hip_stream;
   const int ns = desc->n_samples;
   // group samples by grid
@@ -1654,7 +1682,10 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
       for (int q = 0; q < 6; ++q) g.macro[q] = T(desc->macro_strain[6 * i + q]);
       HIP_TRY(hipMemcpyAsync(c.phase + j * N, desc->phase[i], N, hipMemcpyDeviceToDevice, s));
       Launch<T>::check_phase(c.phase + j * N, N, m.n_phases, hflag, s);
-      Launch<T>::fill_macro(c.eps + j * 6 * N, N, desc->macro_strain + 6 * i, s);
+      if (init && init[i])  // a float32 start (the persistent solve's iterate)
+        Launch<T>::convert_to(c.eps + j * 6 * N, init[i], 0, 6 * N, s);
+      else
+        Launch<T>::fill_macro(c.eps + j * 6 * N, N, desc->macro_strain + 6 * i, s);
     }
     HIP_TRY(hipMemcpyAsync(c.coef, cT.data(), cT.size() * sizeof(PhaseCoef<T>), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(c.coef64, c64.data(), c64.size() * sizeof(PhaseCoef<double>), hipMemcpyHostToDevice, s));
@@ -1796,6 +1827,313 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
   return worst;
 }
 
+// ---------------------------------------------------------------------------
+// persistent batched solve (fe_batch.hip): one cooperative launch for the
+// float32 iteration of every sample, then the float64 verification and, for
+// the samples whose float32 iterate does not verify to tol, float64
+// iterations from that iterate (per-pass launches over those samples only)
+// ---------------------------------------------------------------------------
+struct DevBuffers {
+  std::vector<void*> v;
+  template <typename P>
+  hipError_t alloc(P** p, size_t bytes) {
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, bytes);
+    if (e == hipSuccess) v.push_back(q);
+    *p = static_cast<P*>(q);
+    return e;
+  }
+  ~DevBuffers() {
+    for (void* q : v) (void)hipFree(q);
+  }
+};
+
+fe_status solve_batched_persistent(int op, bool accel, const fe_plan_options& o, const fe_batch_desc* desc,
+                                   double tol, fe_batch_result* results, double* seconds, bool* handled) {
+  *handled = false;
+  if (o.precision != FE_FP32) return FE_OK;
+  const int ns = desc->n_samples;
+  struct PClass {
+    Dims d;
+    std::vector<int> ids;
+    int ncoef = 1;
+  };
+  std::vector<PClass> cls;
+  for (int i = 0; i < ns; ++i) {
+    const fe_grid& g = desc->grids[i];
+    if (!batch_length_ok(g.nx) || !batch_length_ok(g.ny) || !batch_length_ok(g.nz)) return FE_OK;
+    size_t c = 0;
+    for (; c < cls.size(); ++c)
+      if (cls[c].d.nx == g.nx && cls[c].d.ny == g.ny && cls[c].d.nz == g.nz) break;
+    if (c == cls.size()) {
+      if (cls.size() == (size_t)kBatchClasses) return FE_OK;
+      PClass pc;
+      pc.d = make_dims(g.nx, g.ny, g.nz);
+      cls.push_back(pc);
+    }
+    cls[c].ids.push_back(i);
+    cls[c].ncoef = std::max(cls[c].ncoef, desc->materials[i].n_phases);
+  }
+  const int grid = batch_persistent_grid(op, accel);
+  if (grid <= 0) return FE_OK;
+  *handled = true;
+  hipStream_t s = (hipStream_t)o.hip_stream;
+  DevBuffers mem;
+  BatchDev hb;
+  std::memset(&hb, 0, sizeof hb);
+  hb.ncls = (int)cls.size();
+  hb.tol = tol;
+  hb.max_iter = o.max_iter;
+  hb.diverge_window = o.diverge_window;
+  std::vector<PhaseCoef<double>*> coef64(cls.size(), nullptr);
+  int* flag = nullptr;
+  HIP_TRY(mem.alloc(&flag, sizeof(int)));
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+  std::vector<std::vector<float>> host_tables;  // alive until the stream synchronises
+  int first = 0;
+  for (size_t c = 0; c < cls.size(); ++c) {
+    BatchClassDev& C = hb.cls[c];
+    const Dims d = cls[c].d;
+    const int n = (int)cls[c].ids.size();
+    const long long N = d.N;
+    const size_t spec = (size_t)spec_size(d);
+    C.d = d;
+    C.n = n;
+    C.nact = n;
+    C.first = first;
+    first += n;
+    C.ncoef = cls[c].ncoef;
+    batch_class_layout(d, &C.bz, &C.by, &C.bx, &C.bu, &C.zchunk);
+    HIP_TRY(mem.alloc(&C.eps[0], (size_t)n * 6 * N * sizeof(float)));
+    HIP_TRY(mem.alloc(&C.eps[1], (size_t)n * 6 * N * sizeof(float)));
+    HIP_TRY(mem.alloc(&C.R[0], (size_t)n * 3 * N * sizeof(float)));
+    HIP_TRY(mem.alloc(&C.R[1], (size_t)n * 3 * N * sizeof(float)));
+    HIP_TRY(mem.alloc(&C.S, (size_t)n * 3 * spec * sizeof(cpx<float>)));
+    uint8_t* phase = nullptr;
+    HIP_TRY(mem.alloc(&phase, (size_t)n * N));
+    C.phase = phase;
+    HIP_TRY(mem.alloc(&C.partials, (size_t)n * C.bu * 7 * sizeof(double)));
+    PhaseCoef<float>* coef = nullptr;
+    HIP_TRY(mem.alloc(&coef, (size_t)n * C.ncoef * sizeof(PhaseCoef<float>)));
+    C.coef = coef;
+    HIP_TRY(mem.alloc(&coef64[c], (size_t)n * C.ncoef * sizeof(PhaseCoef<double>)));
+    GreenConst<float>* gcon = nullptr;
+    HIP_TRY(mem.alloc(&gcon, (size_t)n * sizeof(GreenConst<float>)));
+    C.gcon = gcon;
+    HIP_TRY(mem.alloc(&C.act, (size_t)n * sizeof(int)));
+    const int dims[3] = {d.nx, d.ny, d.nz};
+    float* wave[3];
+    for (int a = 0; a < 3; ++a) {
+      std::vector<double> tw = twiddles(dims[a]), wv = wave_table(dims[a], op);
+      host_tables.emplace_back(tw.begin(), tw.end());
+      host_tables.emplace_back(wv.begin(), wv.end());
+      cpx<float>* twd = nullptr;
+      HIP_TRY(mem.alloc(&twd, tw.size() * sizeof(float)));
+      HIP_TRY(mem.alloc(&wave[a], wv.size() * sizeof(float)));
+      HIP_TRY(hipMemcpyAsync(twd, host_tables[host_tables.size() - 2].data(), tw.size() * sizeof(float),
+                             hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(wave[a], host_tables.back().data(), wv.size() * sizeof(float), hipMemcpyHostToDevice,
+                             s));
+      C.tw[a] = twd;
+    }
+    C.wt = WaveTables<float>{wave[0], wave[1], wave[2]};
+    std::vector<PhaseCoef<float>> cT((size_t)n * C.ncoef);
+    std::vector<PhaseCoef<double>> c64((size_t)n * C.ncoef);
+    std::vector<GreenConst<float>> gv(n);
+    std::vector<int> idx(n);
+    for (int j = 0; j < n; ++j) {
+      const int i = cls[c].ids[j];
+      idx[j] = j;
+      const fe_materials& m = desc->materials[i];
+      const RefMedium ref = reference_medium(o, accel ? FE_ACCELERATED : FE_DIRECT, m);
+      std::vector<PhaseCoef<double>> pc = phase_coefs(m, ref);
+      for (int q = 0; q < m.n_phases; ++q) {
+        c64[(size_t)j * C.ncoef + q] = pc[q];
+        PhaseCoef<float>& t = cT[(size_t)j * C.ncoef + q];
+        t.lam = float(pc[q].lam);
+        t.mu = float(pc[q].mu);
+        t.dlam = float(pc[q].dlam);
+        t.dmu = float(pc[q].dmu);
+        t.ak = float(pc[q].ak);
+        t.am = float(pc[q].am);
+        t.pad0 = t.pad1 = 0.f;
+      }
+      GreenConst<float>& g = gv[j];
+      g.lam0 = float(ref.lam0);
+      g.mu0 = float(ref.mu0);
+      g.cr = float((ref.lam0 + ref.mu0) / (ref.lam0 + 2.0 * ref.mu0));
+      g.s1 = float(1.0 / (2.0 * ref.mu0));
+      g.s2 = float(ref.lam0 / (2.0 * ref.mu0 * (3.0 * ref.lam0 + 2.0 * ref.mu0)));
+      g.inv_n = float(1.0 / (double)N);
+      for (int q = 0; q < 6; ++q) g.macro[q] = float(desc->macro_strain[6 * i + q]);
+      HIP_TRY(hipMemcpyAsync(phase + (size_t)j * N, desc->phase[i], N, hipMemcpyDeviceToDevice, s));
+      Launch<float>::check_phase(phase + (size_t)j * N, N, m.n_phases, flag, s);
+      Launch<float>::fill_macro(C.eps[0] + (size_t)j * 6 * N, N, desc->macro_strain + 6 * i, s);
+    }
+    HIP_TRY(hipMemcpyAsync(coef, cT.data(), cT.size() * sizeof(PhaseCoef<float>), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(coef64[c], c64.data(), c64.size() * sizeof(PhaseCoef<double>), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(gcon, gv.data(), gv.size() * sizeof(GreenConst<float>), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(C.act, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // the host vectors above go out of scope
+  }
+  int hflag = 0;
+  HIP_TRY(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (hflag) return fail(FE_ERR_INVALID_ARG, "a phase map holds a label >= its n_phases");
+  std::vector<BatchState> st(first);
+  for (BatchState& x : st) {
+    std::memset(&x, 0, sizeof x);
+    x.status = kBatchRunning;
+    x.prev = INFINITY;
+    x.best = INFINITY;
+  }
+  BatchState* dst = nullptr;
+  HIP_TRY(mem.alloc(&dst, st.size() * sizeof(BatchState)));
+  HIP_TRY(hipMemcpyAsync(dst, st.data(), st.size() * sizeof(BatchState), hipMemcpyHostToDevice, s));
+  hb.st = dst;
+  HIP_TRY(mem.alloc(&hb.ctrl, sizeof(int)));
+  HIP_TRY(hipMemsetAsync(hb.ctrl, 0, sizeof(int), s));
+  BatchDev* dbd = nullptr;
+  HIP_TRY(mem.alloc(&dbd, sizeof(BatchDev)));
+  HIP_TRY(hipMemcpyAsync(dbd, &hb, sizeof(BatchDev), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, s));
+  HIP_TRY(launch_batch_persistent(op, accel, dbd, grid, s));
+  HIP_TRY(hipEventRecord(e1, s));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (seconds) *seconds = ms * 1e-3;
+  HIP_TRY(hipMemcpy(st.data(), dst, st.size() * sizeof(BatchState), hipMemcpyDeviceToHost));
+
+  // results of the float32 iteration; the final iterate into parity-0 slots
+  for (size_t c = 0; c < cls.size(); ++c) {
+    const BatchClassDev& C = hb.cls[c];
+    const long long N = C.d.N;
+    for (int j = 0; j < C.n; ++j) {
+      const BatchState& x = st[C.first + j];
+      fe_batch_result& r = results[cls[c].ids[j]];
+      r.status = x.status == kBatchRunning ? FE_NOT_CONVERGED : x.status;
+      r.iterations = x.iterations;
+      r.eta = x.eta;
+      for (int q = 0; q < 6; ++q) r.mean_stress[q] = x.mean[q];
+      if (x.parity)
+        HIP_TRY(hipMemcpyAsync(C.eps[0] + (size_t)j * 6 * N, C.eps[1] + (size_t)j * 6 * N, 6 * N * sizeof(float),
+                               hipMemcpyDeviceToDevice, s));
+    }
+  }
+  // float64 verification of the float32 strains (reusing the class buffers)
+  double* red = nullptr;
+  HIP_TRY(mem.alloc(&red, (size_t)std::max(first, 1) * 8 * sizeof(double)));
+  auto verify = [&](size_t c, std::vector<double>& out) -> fe_status {
+    const BatchClassDev& C = hb.cls[c];
+    const Batch bt{C.act, C.ncoef};
+    std::vector<int> all(C.n);
+    for (int j = 0; j < C.n; ++j) all[j] = j;
+    HIP_TRY(hipMemcpyAsync(C.act, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    const int nb = launch_div64<float>(C.eps[0], C.phase, coef64[c], nullptr, nullptr, C.partials, C.d, op, s, bt, C.n);
+    launch_reduce(C.partials, nb, 7, red, s, C.act, C.n);
+    std::vector<double> h((size_t)C.n * 8);
+    HIP_TRY(hipMemcpyAsync(h.data(), red, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    out.resize(C.n);
+    for (int j = 0; j < C.n; ++j) {
+      double mean[6];
+      for (int q = 0; q < 6; ++q) mean[q] = h[8 * j + 1 + q] / (double)C.d.N;
+      out[j] = std::sqrt(h[8 * j] / (double)C.d.N) / frob(mean);
+    }
+    return FE_OK;
+  };
+  // samples whose float32 strain does not verify: float64 iterations from it
+  std::vector<int> redo;
+  for (size_t c = 0; c < cls.size(); ++c) {
+    std::vector<double> ev;
+    fe_status vs = verify(c, ev);
+    if (vs != FE_OK) return vs;
+    for (int j = 0; j < hb.cls[c].n; ++j) {
+      fe_batch_result& r = results[cls[c].ids[j]];
+      r.eta_verify_fp64 = ev[j];
+      if (o.refine && r.status != FE_DIVERGED && !(ev[j] <= tol) && r.iterations < o.max_iter)
+        redo.push_back((int)((c << 20) | j));
+    }
+  }
+  if (!redo.empty()) {
+    const int nr = (int)redo.size();
+    std::vector<fe_grid> grids(nr);
+    std::vector<const uint8_t*> phases(nr);
+    std::vector<fe_materials> mats(nr);
+    std::vector<double> macro((size_t)6 * nr);
+    std::vector<void*> out64(nr);
+    std::vector<const float*> init(nr);
+    std::vector<fe_batch_result> sub(nr);
+    for (int k = 0; k < nr; ++k) {
+      const size_t c = (size_t)(redo[k] >> 20);
+      const int j = redo[k] & ((1 << 20) - 1), i = cls[c].ids[j];
+      grids[k] = desc->grids[i];
+      phases[k] = desc->phase[i];
+      mats[k] = desc->materials[i];
+      for (int q = 0; q < 6; ++q) macro[6 * k + q] = desc->macro_strain[6 * i + q];
+      double* o64 = nullptr;
+      HIP_TRY(mem.alloc(&o64, (size_t)6 * hb.cls[c].d.N * sizeof(double)));
+      out64[k] = o64;
+      init[k] = hb.cls[c].eps[0] + (size_t)j * 6 * hb.cls[c].d.N;
+    }
+    fe_batch_desc sd;
+    sd.n_samples = nr;
+    sd.grids = grids.data();
+    sd.phase = phases.data();
+    sd.materials = mats.data();
+    sd.macro_strain = macro.data();
+    sd.strain = out64.data();
+    fe_plan_options o64 = o;
+    o64.precision = FE_FP64;
+    double sec64 = 0.0;
+    const fe_status st64 = solve_batched_impl<double>(op, accel, o64, &sd, tol, sub.data(), &sec64, init.data());
+    if (st64 < 0) return st64;
+    if (seconds) *seconds += sec64;
+    for (int k = 0; k < nr; ++k) {
+      const size_t c = (size_t)(redo[k] >> 20);
+      const int j = redo[k] & ((1 << 20) - 1);
+      const long long N = hb.cls[c].d.N;
+      Launch<float>::convert_to(hb.cls[c].eps[0] + (size_t)j * 6 * N, out64[k], 1, 6 * N, s);
+      fe_batch_result& r = results[cls[c].ids[j]];
+      r.iterations += sub[k].iterations;
+      r.eta = sub[k].eta;
+      for (int q = 0; q < 6; ++q) r.mean_stress[q] = sub[k].mean_stress[q];
+      r.status = sub[k].status;
+    }
+    for (size_t c = 0; c < cls.size(); ++c) {  // the returned float32 strains, verified again
+      std::vector<double> ev;
+      fe_status vs = verify(c, ev);
+      if (vs != FE_OK) return vs;
+      for (int j = 0; j < hb.cls[c].n; ++j) {
+        fe_batch_result& r = results[cls[c].ids[j]];
+        r.eta_verify_fp64 = ev[j];
+        if (r.status == FE_OK && !(ev[j] <= tol)) r.status = FE_NOT_CONVERGED;  // float32 storage floor
+      }
+    }
+  }
+  for (size_t c = 0; c < cls.size(); ++c) {
+    const long long N = hb.cls[c].d.N;
+    for (int j = 0; j < hb.cls[c].n; ++j) {
+      const int i = cls[c].ids[j];
+      if (desc->strain && desc->strain[i])
+        HIP_TRY(hipMemcpyAsync(desc->strain[i], hb.cls[c].eps[0] + (size_t)j * 6 * N, 6 * N * sizeof(float),
+                               hipMemcpyDeviceToDevice, s));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  fe_status worst = FE_OK;
+  for (int i = 0; i < ns; ++i)
+    if (results[i].status > worst) worst = (fe_status)results[i].status;
+  return worst;
+}
+
 }  // namespace
 
 extern "C" fe_status fe_solve_batched(fe_discretization disc, fe_scheme scheme, const fe_plan_options* opt,
@@ -1839,5 +2177,9 @@ extern "C" fe_status fe_solve_batched(fe_discretization disc, fe_scheme scheme, 
   }
   const int op = disc == FE_GREEN_WP ? OP_WP : OP_ROT;
   if (o.precision == FE_FP64) return solve_batched_impl<double>(op, scheme == FE_ACCELERATED, o, desc, tol, results, seconds);
+  bool handled = false;
+  const fe_status ps =
+      solve_batched_persistent(op, scheme == FE_ACCELERATED, o, desc, tol, results, seconds, &handled);
+  if (handled) return ps;
   return solve_batched_impl<float>(op, scheme == FE_ACCELERATED, o, desc, tol, results, seconds);
 }

@@ -52,15 +52,13 @@ struct alignas(4 * sizeof(T)) cpx2 {
 // ---------------------------------------------------------------------------
 // y: complex transform of the half spectrum along y, in place
 // ---------------------------------------------------------------------------
+// One workgroup (tile lb) of the y pass on one sample's spectra S.
 template <typename T, int N, bool INV>
-__global__ __launch_bounds__((StridedCfg<T, N, true>::NT)) void k_ypass(cpx<T>* __restrict__ S, Dims d,
-                                                                      const cpx<T>* __restrict__ tw, Batch bt) {
+__device__ __forceinline__ void ypass_body(cpx<T>* __restrict__ S, const Dims& d, const cpx<T>* __restrict__ tw,
+                                           cpx<T>* lds, int lb) {
   using C = StridedCfg<T, N, true>;
-  if (bt.active) S += (long long)bt.active[blockIdx.y] * (gridDim.x / (((d.nx + C::TX - 1) / C::TX) * d.H)) * spec_size(d);
-  __shared__ cpx<T> lds[N * C::TX];
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
   const int ntx = (d.nx + C::TX - 1) / C::TX;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);  // x-neighbour tiles share 128-byte lines: same L2
   const int xt = lb % ntx;
   const int rest = lb / ntx;
   const int mz = rest % d.H;
@@ -79,26 +77,30 @@ __global__ __launch_bounds__((StridedCfg<T, N, true>::NT)) void k_ypass(cpx<T>* 
   }
 }
 
+template <typename T, int N, bool INV>
+__global__ __launch_bounds__((StridedCfg<T, N, true>::NT)) void k_ypass(cpx<T>* __restrict__ S, Dims d,
+                                                                      const cpx<T>* __restrict__ tw, Batch bt) {
+  using C = StridedCfg<T, N, true>;
+  if (bt.active) S += (long long)bt.active[blockIdx.y] * (gridDim.x / (((d.nx + C::TX - 1) / C::TX) * d.H)) * spec_size(d);
+  __shared__ cpx<T> lds[N * C::TX];
+  // x-neighbour tiles share 128-byte lines: same L2
+  ypass_body<T, N, INV>(S, d, tw, lds, xcd_block(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // z: real-to-complex.  Two adjacent real x-columns are one complex column
 // z = a + i b; after the transform A(m) = (Z(m) + conj Z(-m))/2 and
 // B(m) = (Z(m) - conj Z(-m))/(2i) for m in [0, nz/2].
 // ---------------------------------------------------------------------------
+// One workgroup (tile lb) of the real-to-complex z pass on one sample (R its
+// real planes, S its half spectra).
 template <typename T, int N>
-__global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __restrict__ R, cpx<T>* __restrict__ S,
-                                                               Dims d, const cpx<T>* __restrict__ tw, Batch bt) {
+__device__ __forceinline__ void zr2c_body(const T* __restrict__ R, cpx<T>* __restrict__ S, const Dims& d,
+                                          const cpx<T>* __restrict__ tw, cpx<T>* lds, int lb) {
   using C = StridedCfg<T, N>;
-  if (bt.active) {
-    const long long nc = gridDim.x / (((d.nx / 2 + C::TX - 1) / C::TX) * d.ny);
-    const long long smp = bt.active[blockIdx.y];
-    R += smp * nc * d.N;
-    S += smp * nc * spec_size(d);
-  }
-  __shared__ cpx<T> lds[N * C::TX];
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
   const int npair = d.nx / 2;
   const int ntx = (npair + C::TX - 1) / C::TX;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);  // x-neighbour tiles share 128-byte lines: same L2
   const int xt = lb % ntx;
   const int rest = lb / ntx;
   const int y = rest % d.ny;
@@ -130,10 +132,9 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __rest
   }
 }
 
-// z: complex-to-real (unnormalised inverse): Z(m) = A(m) + i B(m),
-// Z(nz-m) = conj A(m) + i conj B(m); the inverse transform of Z is a + i b.
+
 template <typename T, int N>
-__global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* __restrict__ S, T* __restrict__ R,
+__global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __restrict__ R, cpx<T>* __restrict__ S,
                                                                Dims d, const cpx<T>* __restrict__ tw, Batch bt) {
   using C = StridedCfg<T, N>;
   if (bt.active) {
@@ -143,10 +144,19 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* _
     S += smp * nc * spec_size(d);
   }
   __shared__ cpx<T> lds[N * C::TX];
+  // x-neighbour tiles share 128-byte lines: same L2
+  zr2c_body<T, N>(R, S, d, tw, lds, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// z: complex-to-real (unnormalised inverse): Z(m) = A(m) + i B(m),
+// Z(nz-m) = conj A(m) + i conj B(m); the inverse transform of Z is a + i b.
+template <typename T, int N>
+__device__ __forceinline__ void zc2r_body(const cpx<T>* __restrict__ S, T* __restrict__ R, const Dims& d,
+                                          const cpx<T>* __restrict__ tw, cpx<T>* lds, int lb) {
+  using C = StridedCfg<T, N>;
   const int col = threadIdx.x % C::TX, t = threadIdx.x / C::TX;
   const int npair = d.nx / 2;
   const int ntx = (npair + C::TX - 1) / C::TX;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);  // x-neighbour tiles share 128-byte lines: same L2
   const int xt = lb % ntx;
   const int rest = lb / ntx;
   const int y = rest % d.ny;
@@ -190,6 +200,22 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* _
   }
 }
 
+
+template <typename T, int N>
+__global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* __restrict__ S, T* __restrict__ R,
+                                                               Dims d, const cpx<T>* __restrict__ tw, Batch bt) {
+  using C = StridedCfg<T, N>;
+  if (bt.active) {
+    const long long nc = gridDim.x / (((d.nx / 2 + C::TX - 1) / C::TX) * d.ny);
+    const long long smp = bt.active[blockIdx.y];
+    R += smp * nc * d.N;
+    S += smp * nc * spec_size(d);
+  }
+  __shared__ cpx<T> lds[N * C::TX];
+  // x-neighbour tiles share 128-byte lines: same L2
+  zc2r_body<T, N>(S, R, d, tw, lds, xcd_block(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // x: forward transform of each contiguous x-line, Green operator per
 // frequency in registers, inverse transform.
@@ -209,23 +235,15 @@ __device__ __forceinline__ bool xline_of(const Dims& d, int line, int& mz, int& 
   my = r % d.ny;
   return true;
 }
+// One workgroup (line block bx) of the x pass with the Green operator of the
+// displacement form on one sample's spectra S; lds holds 3 LPB LINE values.
 template <typename T, int N, int OP>
-__global__ __launch_bounds__((LineCfg<T, N, 3>::NT)) void k_xgreen3(cpx<T>* __restrict__ S, Dims d,
-                                                                  const cpx<T>* __restrict__ tw, WaveTables<T> wt,
-                                                                  GreenConst<T> g, Batch bt,
-                                                                  const GreenConst<T>* __restrict__ gs) {
+__device__ __forceinline__ void xgreen3_body(cpx<T>* __restrict__ S, const Dims& d, const cpx<T>* __restrict__ tw,
+                                             const WaveTables<T>& wt, const GreenConst<T>& g, cpx<T>* lds, int bx) {
   using C = LineCfg<T, N, 3>;
-  if (bt.active) {
-    const long long smp = bt.active[blockIdx.y];
-    S += smp * 3 * spec_size(d);
-    if (gs) g = gs[smp];
-  }
-  // the three components exchange through LDS together (51 KiB at 512):
-  // a third of the barriers of taking turns
-  __shared__ cpx<T> lds[3 * C::LPB * C::LINE];
   const int t = threadIdx.x % C::P, l = threadIdx.x / C::P;
   const int nlines = d.Hp * d.ny;
-  const int line = blockIdx.x * C::LPB + l;
+  const int line = bx * C::LPB + l;
   int mz, my;
   const bool ok = xline_of(d, line, mz, my);
   const long long cs = (long long)nlines * N;
@@ -251,6 +269,24 @@ __global__ __launch_bounds__((LineCfg<T, N, 3>::NT)) void k_xgreen3(cpx<T>* __re
 #pragma unroll
       for (int m = 0; m < C::E; ++m) base[c * cs + m * C::P] = v[c][m];
   }
+}
+
+
+template <typename T, int N, int OP>
+__global__ __launch_bounds__((LineCfg<T, N, 3>::NT)) void k_xgreen3(cpx<T>* __restrict__ S, Dims d,
+                                                                  const cpx<T>* __restrict__ tw, WaveTables<T> wt,
+                                                                  GreenConst<T> g, Batch bt,
+                                                                  const GreenConst<T>* __restrict__ gs) {
+  using C = LineCfg<T, N, 3>;
+  if (bt.active) {
+    const long long smp = bt.active[blockIdx.y];
+    S += smp * 3 * spec_size(d);
+    if (gs) g = gs[smp];
+  }
+  // the three components exchange through LDS together (51 KiB at 512):
+  // a third of the barriers of taking turns
+  __shared__ cpx<T> lds[3 * C::LPB * C::LINE];
+  xgreen3_body<T, N, OP>(S, d, tw, wt, g, lds, blockIdx.x);
 }
 
 template <typename T, int N, int OP>

@@ -132,3 +132,47 @@ def test_batched_rejects_bad_labels():
     _, status, _ = fe.solve_batched(samples, 1e-6, raise_on_error=False)
     assert status == fe.FE_ERR_INVALID_ARG
     assert "label" in fe.last_error()
+
+
+def test_batch_outside_the_persistent_lengths_matches_single_solves():
+    """A batch with a grid length the persistent kernel is not built for (8)
+    runs one launch per pass; samples still equal single solves bit for bit."""
+    a, _ = boolean_spheres((8, 16, 16), 2.0, 0.2, 21)
+    b, _ = boolean_spheres((16, 16, 16), 3.0, 0.25, 22)
+    specs = [(a, [1.0, 10.0], [0.3, 0.3], [0, 0, 0, 0, 0, 1.0]), (b, [1.0, 5.0], [0.3, 0.3], [1.0, 0, 0, 0, 0, 0])]
+    res, status, _, eps = _batched(specs, "R", "AS", "fp32", 1e-5, 2000)
+    assert status == fe.FE_OK
+    for (ph, E, nu, macro), rb, eb in zip(specs, res, eps):
+        rs, es = _single(ph, E, nu, macro, "R", "AS", "fp32", 1e-5, 2000)
+        assert rb.iterations == rs.iterations and rb.eta == rs.eta and np.array_equal(eb, es)
+
+
+def test_float64_continuation_reaches_the_tolerance():
+    """High-contrast samples whose float32 iteration stalls above 1e-6 (the
+    float32 floor) continue in float64 from their float32 iterate: every
+    returned strain verifies to 1e-6 in float64, and without the
+    continuation some do not."""
+    from microstructure import batch_samples
+
+    samples = [s for s in batch_samples(24, 7001, sizes=(32, 48))]
+    specs = [(s.phase, [1.0, s.contrast], [s.nu, s.nu], s.macro_strain) for s in samples]
+    plain, _, _, _ = _batched_opts(specs, "R", "AS", 1e-6, 2000, refine=False)
+    res, status, _, eps = _batched_opts(specs, "R", "AS", 1e-6, 2000, refine=True)
+    assert status == fe.FE_OK, [(r.status, r.iterations, r.eta_verify_fp64) for r in res]
+    assert all(r.eta_verify_fp64 <= 1e-6 for r in res)
+    assert any(r.eta_verify_fp64 > 1e-6 for r in plain)
+    for rp, rr, e in zip(plain, res, eps):
+        assert rr.iterations >= rp.iterations and np.isfinite(e).all()
+
+
+def _batched_opts(specs, op, scheme, tol, max_iter, refine):
+    samples, outs = [], []
+    for ph, E, nu, macro in specs:
+        nz, ny, nx = ph.shape
+        eps = torch.empty((6, nz, ny, nx), dtype=torch.float32, device="cuda")
+        outs.append(eps)
+        samples.append(fe.BatchSampleSpec(_dev(ph), E, nu, macro, eps))
+    res, status, sec = fe.solve_batched(samples, tol, green=op, scheme=scheme, precision="fp32", max_iter=max_iter,
+                                        refine=refine, raise_on_error=False)
+    torch.cuda.synchronize()
+    return res, status, sec, [e.cpu().numpy() for e in outs]
