@@ -129,7 +129,19 @@ typedef struct {
                              re-anchor in float64 and iterate in float32 on the
                              correction (default 1; 0 = plain float32)         */
   void* hip_stream;       /* hipStream_t to run on; NULL = the null stream        */
+  int32_t batch_launch;   /* fe_solve_batched, float32: fe_batch_launch, default
+                             FE_BATCH_PER_PASS                                  */
 } fe_plan_options;
+
+/* How fe_solve_batched runs the float32 iteration of a batch. */
+typedef enum {
+  FE_BATCH_PER_PASS = 0,   /* one launch per pass per iteration over the active
+                              samples of each grid, eta read back per iteration */
+  FE_BATCH_PERSISTENT = 1  /* one cooperative persistent launch for all passes of
+                              all iterations, eta and retirement on the device;
+                              grid lengths 16, 24, 32, 48, 64, 96, 128 and at
+                              most 8 distinct grids (else the per-pass launch) */
+} fe_batch_launch;
 
 /* Passes of one iteration, indices of fe_result.pass_seconds / pass_launches. */
 enum {
@@ -235,18 +247,15 @@ fe_status fe_effective_stiffness(fe_plan* plan, const uint8_t* phase, fe_materia
  * iteration cap is reached, eta rises for diverge_window checks
  * (FE_DIVERGED), or eta has not fallen by 5% over 100 iterations (the
  * float32 storage floor: FE_NOT_CONVERGED).
- *   Float32 batches whose grid lengths are each one of 16, 24, 32, 48, 64,
- *   96, 128 (at most 8 distinct grids) run as ONE cooperative persistent
- *   launch: every pass of every iteration of all samples, with each sample's
- *   eta, stop rules and retirement on the device.  Then the float64
- *   verification; with opt->refine (the default) a sample whose float32
- *   strain does not verify to tol continues with float64 fields from it
- *   (one launch per pass per iteration over those samples only), its strain
- *   is returned rounded to float32, verified again, and FE_OK only if that
- *   verification meets tol; iterations counts both phases.
- *   Other batches (float64, other lengths): one launch per pass per
- *   iteration over the active samples of each grid, eta read back once per
- *   iteration, no float64 continuation.
+ *   Float32: the iteration runs as opt->batch_launch says (fe_batch_launch);
+ *   then every returned strain is verified in float64, and with opt->refine
+ *   (the default) a sample whose float32 strain does not verify to tol
+ *   continues with float64 fields from it (one launch per pass per iteration
+ *   over those samples only); its strain is returned rounded to float32,
+ *   verified again, and FE_OK only if that verification meets tol;
+ *   iterations counts both phases.
+ *   Float64: one launch per pass per iteration (FE_BATCH_PERSISTENT gives
+ *   FE_ERR_UNSUPPORTED).
  *   desc->phase[i]   device, N_i uint8 labels of sample i
  *   desc->strain[i]  device, 6*N_i of the requested precision, receives eps of
  *                    sample i (NULL: not returned)

@@ -55,7 +55,11 @@ class FePlanOptions(C.Structure):
         ("timing", C.c_int32),
         ("refine", C.c_int32),
         ("hip_stream", C.c_void_p),
+        ("batch_launch", C.c_int32),
     ]
+
+
+BATCH_LAUNCH = {"per_pass": 0, "persistent": 1}
 
 
 class FeMaterials(C.Structure):
@@ -389,11 +393,15 @@ def _options(lib, precision, max_iter, ref_rule, ds_beta, E0, nu0, diverge_windo
 
 
 def solve_batched(samples, tol, green="R", scheme="AS", precision="fp32", max_iter=1000, ref_rule="paper",
-                  ds_beta=0.5, E0=0.0, nu0=0.25, diverge_window=50, stream=None, raise_on_error=True, refine=True):
+                  ds_beta=0.5, E0=0.0, nu0=0.25, diverge_window=50, stream=None, raise_on_error=True, refine=True,
+                  launch="per_pass"):
     """fe_solve_batched over a list of BatchSampleSpec; returns (results, status,
     seconds) with one Result per sample (eta_history, pass timings empty).
     ``refine``: float32 samples whose strain does not verify to tol continue
-    in float64 (fe_plan_options.refine)."""
+    in float64 (fe_plan_options.refine).  ``launch``: "per_pass" or
+    "persistent" (fe_plan_options.batch_launch)."""
+    if launch not in BATCH_LAUNCH:
+        raise ValueError(f"launch must be one of {sorted(BATCH_LAUNCH)}")
     lib = load_library()
     n = len(samples)
     if n == 0:
@@ -429,6 +437,7 @@ def solve_batched(samples, tol, green="R", scheme="AS", precision="fp32", max_it
             macro[6 * i + q] = mv[q]
     desc = FeBatchDesc(n, grids, phases, mats, macro, strains)
     opt = _options(lib, precision, max_iter, ref_rule, ds_beta, E0, nu0, diverge_window, stream, refine)
+    opt.batch_launch = BATCH_LAUNCH[launch]
     res = (FeBatchResult * n)()
     sec = C.c_double(0.0)
     s = lib.fe_solve_batched(GREEN[green], SCHEME[scheme], C.byref(opt), C.byref(desc), float(tol), res,

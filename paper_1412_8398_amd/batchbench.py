@@ -8,11 +8,12 @@ Poisson ratio U[0.2, 0.4] for both phases, sphere radius U[3, 8] voxels, one
 unit macroscopic strain among the six (microstructure.batch_samples).  The
 accelerated scheme with the rotated operator, float32 fields, tolerance 1e-6.
 
-Two runs of fe_solve_batched over the whole batch: refine off (the float32
-iteration alone: one persistent launch) and refine on (then float64
-iterations for the samples whose float32 strain does not verify to the
-tolerance).  Reports device seconds, voxel-iterations per second, the status
-counts and the float64-verified eta of the returned strains.
+Runs of fe_solve_batched over the whole batch, each float32 launch (one per
+pass; one cooperative persistent launch) with refine off (the float32
+iteration alone) and on (then float64 iterations for the samples whose
+float32 strain does not verify to the tolerance).  Reports device seconds,
+voxel-iterations per second, the status counts and the float64-verified eta
+of the returned strains.
 """
 from __future__ import annotations
 
@@ -53,24 +54,25 @@ def main(argv=None):
              for p, s, e in zip(phases, samples, outs)]
     rep = {"n": args.n, "seed": args.seed, "tol": args.tol, "max_iter": args.max_iter,
            "sizes": {str(L): sum(1 for s in samples if s.L == L) for L in (32, 48, 64, 96)}}
-    for refine in (False, True):
+    for launch, refine in (("per_pass", False), ("persistent", False), ("per_pass", True), ("persistent", True)):
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         res, status, sec = fe.solve_batched(specs, args.tol, green="R", scheme="AS", precision="fp32",
-                                            max_iter=args.max_iter, refine=refine, raise_on_error=False)
+                                            max_iter=args.max_iter, refine=refine, raise_on_error=False,
+                                            launch=launch)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         its = np.array([r.iterations for r in res])
         st = np.array([r.status for r in res])
         ev = np.array([r.eta_verify_fp64 for r in res])
         vox_it = float(sum(s.L ** 3 * r.iterations for s, r in zip(samples, res)))
-        row = {"refine": refine, "device_seconds": round(sec, 4), "wall_seconds": round(wall, 3),
+        row = {"launch": launch, "refine": refine, "device_seconds": round(sec, 4), "wall_seconds": round(wall, 3),
                "voxel_iterations": vox_it, "gvoxel_iter_per_s": round(vox_it / sec / 1e9, 2),
                "status_counts": {fe.status_string(int(k)): int(np.sum(st == k)) for k in np.unique(st)},
                "iterations_mean": float(its.mean()), "iterations_max": int(its.max()),
                "eta_verify_fp64_max": float(ev.max()), "eta_verify_fp64_median": float(np.median(ev)),
                "verified_to_tol": int(np.sum(ev <= args.tol))}
-        rep["refine" if refine else "float32"] = row
+        rep[f"{launch}_{'refine' if refine else 'float32'}"] = row
         print(json.dumps(row), flush=True)
     if args.out:
         with open(args.out, "w") as fh:

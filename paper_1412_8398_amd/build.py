@@ -27,6 +27,9 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-Wall",
     "-Wno-unused-function",
+    # fused multiply-adds only where one source expression has them, so an
+    # inlined body rounds the same in every kernel that includes it
+    "-ffp-contract=on",
     # no packed-FP32 instructions (v_pk_*_f32) in any HIP code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE,

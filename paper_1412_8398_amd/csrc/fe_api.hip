@@ -202,6 +202,7 @@ extern "C" void fe_plan_options_default(fe_plan_options* o) {
   o->timing = 0;
   o->refine = 1;
   o->hip_stream = nullptr;
+  o->batch_launch = FE_BATCH_PER_PASS;
 }
 
 static hipError_t dmalloc(fe_plan* p, void** ptr, size_t bytes) {
@@ -419,6 +420,7 @@ static fe_status validate_materials(const fe_materials& m) {
 
 // Frobenius norm of a symmetric tensor given in Voigt order (off-diagonals twice).
 static double frob(const double* s) {
+#pragma clang fp contract(off)  // the roundings of the device's eta in batched solves
   return std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
 }
 
@@ -1828,10 +1830,11 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
 }
 
 // ---------------------------------------------------------------------------
-// persistent batched solve (fe_batch.hip): one cooperative launch for the
-// float32 iteration of every sample, then the float64 verification and, for
-// the samples whose float32 iterate does not verify to tol, float64
-// iterations from that iterate (per-pass launches over those samples only)
+// float32 batched solve: the float32 iteration of every sample (one launch
+// per pass, or one cooperative persistent launch, fe_batch.hip), then the
+// float64 verification and, for the samples whose float32 iterate does not
+// verify to tol, float64 iterations from that iterate (per-pass launches over
+// those samples only)
 // ---------------------------------------------------------------------------
 struct DevBuffers {
   std::vector<void*> v;
@@ -1848,47 +1851,33 @@ struct DevBuffers {
   }
 };
 
-fe_status solve_batched_persistent(int op, bool accel, const fe_plan_options& o, const fe_batch_desc* desc,
-                                   double tol, fe_batch_result* results, double* seconds, bool* handled) {
-  *handled = false;
-  if (o.precision != FE_FP32) return FE_OK;
-  const int ns = desc->n_samples;
-  struct PClass {
-    Dims d;
-    std::vector<int> ids;
-    int ncoef = 1;
-  };
-  std::vector<PClass> cls;
-  for (int i = 0; i < ns; ++i) {
-    const fe_grid& g = desc->grids[i];
-    if (!batch_length_ok(g.nx) || !batch_length_ok(g.ny) || !batch_length_ok(g.nz)) return FE_OK;
-    size_t c = 0;
-    for (; c < cls.size(); ++c)
-      if (cls[c].d.nx == g.nx && cls[c].d.ny == g.ny && cls[c].d.nz == g.nz) break;
-    if (c == cls.size()) {
-      if (cls.size() == (size_t)kBatchClasses) return FE_OK;
-      PClass pc;
-      pc.d = make_dims(g.nx, g.ny, g.nz);
-      cls.push_back(pc);
-    }
-    cls[c].ids.push_back(i);
-    cls[c].ncoef = std::max(cls[c].ncoef, desc->materials[i].n_phases);
-  }
-  const int grid = batch_persistent_grid(op, accel);
-  if (grid <= 0) return FE_OK;
-  *handled = true;
+// samples of one grid: the returned float32 iterates and what the float64
+// verification reads
+struct F32Class {
+  Dims d;
+  std::vector<int> ids;
+  int ncoef = 1;
+  float* eps = nullptr;  // [sample][6][N]
+  uint8_t* phase = nullptr;
+  PhaseCoef<double>* coef64 = nullptr;
+  double* partials = nullptr;  // [sample][bu][7], bu: divergence workgroups per sample (at most)
+  int* act = nullptr;
+  int bu = 0;
+};
+
+// The float32 iteration of every sample in one cooperative launch: grid
+// classes cls (at most kBatchClasses, lengths batch_length_ok), iterates
+// returned in cls[c].eps with results (status, iterations, eta, mean stress).
+static fe_status run_persistent(int op, bool accel, const fe_plan_options& o, const fe_batch_desc* desc, double tol,
+                                std::vector<F32Class>& cls, int grid, DevBuffers& mem, fe_batch_result* results,
+                                double* seconds) {
   hipStream_t s = (hipStream_t)o.hip_stream;
-  DevBuffers mem;
   BatchDev hb;
   std::memset(&hb, 0, sizeof hb);
   hb.ncls = (int)cls.size();
   hb.tol = tol;
   hb.max_iter = o.max_iter;
   hb.diverge_window = o.diverge_window;
-  std::vector<PhaseCoef<double>*> coef64(cls.size(), nullptr);
-  int* flag = nullptr;
-  HIP_TRY(mem.alloc(&flag, sizeof(int)));
-  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
   std::vector<std::vector<float>> host_tables;  // alive until the stream synchronises
   int first = 0;
   for (size_t c = 0; c < cls.size(); ++c) {
@@ -1904,23 +1893,20 @@ fe_status solve_batched_persistent(int op, bool accel, const fe_plan_options& o,
     first += n;
     C.ncoef = cls[c].ncoef;
     batch_class_layout(d, &C.bz, &C.by, &C.bx, &C.bu, &C.zchunk);
-    HIP_TRY(mem.alloc(&C.eps[0], (size_t)n * 6 * N * sizeof(float)));
+    C.eps[0] = cls[c].eps;
     HIP_TRY(mem.alloc(&C.eps[1], (size_t)n * 6 * N * sizeof(float)));
     HIP_TRY(mem.alloc(&C.R[0], (size_t)n * 3 * N * sizeof(float)));
     HIP_TRY(mem.alloc(&C.R[1], (size_t)n * 3 * N * sizeof(float)));
     HIP_TRY(mem.alloc(&C.S, (size_t)n * 3 * spec * sizeof(cpx<float>)));
-    uint8_t* phase = nullptr;
-    HIP_TRY(mem.alloc(&phase, (size_t)n * N));
-    C.phase = phase;
-    HIP_TRY(mem.alloc(&C.partials, (size_t)n * C.bu * 7 * sizeof(double)));
+    C.phase = cls[c].phase;
+    C.partials = cls[c].partials;
+    C.act = cls[c].act;
     PhaseCoef<float>* coef = nullptr;
     HIP_TRY(mem.alloc(&coef, (size_t)n * C.ncoef * sizeof(PhaseCoef<float>)));
     C.coef = coef;
-    HIP_TRY(mem.alloc(&coef64[c], (size_t)n * C.ncoef * sizeof(PhaseCoef<double>)));
     GreenConst<float>* gcon = nullptr;
     HIP_TRY(mem.alloc(&gcon, (size_t)n * sizeof(GreenConst<float>)));
     C.gcon = gcon;
-    HIP_TRY(mem.alloc(&C.act, (size_t)n * sizeof(int)));
     const int dims[3] = {d.nx, d.ny, d.nz};
     float* wave[3];
     for (int a = 0; a < 3; ++a) {
@@ -1938,7 +1924,6 @@ fe_status solve_batched_persistent(int op, bool accel, const fe_plan_options& o,
     }
     C.wt = WaveTables<float>{wave[0], wave[1], wave[2]};
     std::vector<PhaseCoef<float>> cT((size_t)n * C.ncoef);
-    std::vector<PhaseCoef<double>> c64((size_t)n * C.ncoef);
     std::vector<GreenConst<float>> gv(n);
     std::vector<int> idx(n);
     for (int j = 0; j < n; ++j) {
@@ -1948,7 +1933,6 @@ fe_status solve_batched_persistent(int op, bool accel, const fe_plan_options& o,
       const RefMedium ref = reference_medium(o, accel ? FE_ACCELERATED : FE_DIRECT, m);
       std::vector<PhaseCoef<double>> pc = phase_coefs(m, ref);
       for (int q = 0; q < m.n_phases; ++q) {
-        c64[(size_t)j * C.ncoef + q] = pc[q];
         PhaseCoef<float>& t = cT[(size_t)j * C.ncoef + q];
         t.lam = float(pc[q].lam);
         t.mu = float(pc[q].mu);
@@ -1966,19 +1950,13 @@ fe_status solve_batched_persistent(int op, bool accel, const fe_plan_options& o,
       g.s2 = float(ref.lam0 / (2.0 * ref.mu0 * (3.0 * ref.lam0 + 2.0 * ref.mu0)));
       g.inv_n = float(1.0 / (double)N);
       for (int q = 0; q < 6; ++q) g.macro[q] = float(desc->macro_strain[6 * i + q]);
-      HIP_TRY(hipMemcpyAsync(phase + (size_t)j * N, desc->phase[i], N, hipMemcpyDeviceToDevice, s));
-      Launch<float>::check_phase(phase + (size_t)j * N, N, m.n_phases, flag, s);
       Launch<float>::fill_macro(C.eps[0] + (size_t)j * 6 * N, N, desc->macro_strain + 6 * i, s);
     }
     HIP_TRY(hipMemcpyAsync(coef, cT.data(), cT.size() * sizeof(PhaseCoef<float>), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(coef64[c], c64.data(), c64.size() * sizeof(PhaseCoef<double>), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(gcon, gv.data(), gv.size() * sizeof(GreenConst<float>), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(C.act, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));  // the host vectors above go out of scope
   }
-  int hflag = 0;
-  HIP_TRY(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
-  if (hflag) return fail(FE_ERR_INVALID_ARG, "a phase map holds a label >= its n_phases");
   std::vector<BatchState> st(first);
   for (BatchState& x : st) {
     std::memset(&x, 0, sizeof x);
@@ -1990,8 +1968,10 @@ fe_status solve_batched_persistent(int op, bool accel, const fe_plan_options& o,
   HIP_TRY(mem.alloc(&dst, st.size() * sizeof(BatchState)));
   HIP_TRY(hipMemcpyAsync(dst, st.data(), st.size() * sizeof(BatchState), hipMemcpyHostToDevice, s));
   hb.st = dst;
-  HIP_TRY(mem.alloc(&hb.ctrl, sizeof(int)));
-  HIP_TRY(hipMemsetAsync(hb.ctrl, 0, sizeof(int), s));
+  HIP_TRY(mem.alloc(&hb.ctrl, 2 * sizeof(int)));
+  HIP_TRY(hipMemsetAsync(hb.ctrl, 0, 2 * sizeof(int), s));
+  HIP_TRY(mem.alloc(&hb.bar, sizeof(unsigned long long)));
+  HIP_TRY(hipMemsetAsync(hb.bar, 0, sizeof(unsigned long long), s));
   BatchDev* dbd = nullptr;
   HIP_TRY(mem.alloc(&dbd, sizeof(BatchDev)));
   HIP_TRY(hipMemcpyAsync(dbd, &hb, sizeof(BatchDev), hipMemcpyHostToDevice, s));
@@ -2008,11 +1988,12 @@ fe_status solve_batched_persistent(int op, bool accel, const fe_plan_options& o,
   HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (seconds) *seconds = ms * 1e-3;
+  *seconds = ms * 1e-3;
+  int hctrl[2] = {0, 0};
+  HIP_TRY(hipMemcpy(hctrl, hb.ctrl, sizeof hctrl, hipMemcpyDeviceToHost));
+  if (hctrl[1]) return fail(FE_ERR_DEVICE, "persistent batched solve: a grid barrier timed out");
   HIP_TRY(hipMemcpy(st.data(), dst, st.size() * sizeof(BatchState), hipMemcpyDeviceToHost));
-
-  // results of the float32 iteration; the final iterate into parity-0 slots
-  for (size_t c = 0; c < cls.size(); ++c) {
+  for (size_t c = 0; c < cls.size(); ++c) {  // results; the final iterate into the returned slot
     const BatchClassDev& C = hb.cls[c];
     const long long N = C.d.N;
     for (int j = 0; j < C.n; ++j) {
@@ -2027,39 +2008,110 @@ fe_status solve_batched_persistent(int op, bool accel, const fe_plan_options& o,
                                hipMemcpyDeviceToDevice, s));
     }
   }
-  // float64 verification of the float32 strains (reusing the class buffers)
+  return FE_OK;
+}
+
+fe_status solve_batched_f32(int op, bool accel, const fe_plan_options& o, const fe_batch_desc* desc, double tol,
+                            fe_batch_result* results, double* seconds) {
+  const int ns = desc->n_samples;
+  hipStream_t s = (hipStream_t)o.hip_stream;
+  std::vector<F32Class> cls;
+  for (int i = 0; i < ns; ++i) {
+    const fe_grid& g = desc->grids[i];
+    size_t c = 0;
+    for (; c < cls.size(); ++c)
+      if (cls[c].d.nx == g.nx && cls[c].d.ny == g.ny && cls[c].d.nz == g.nz) break;
+    if (c == cls.size()) {
+      F32Class fc;
+      fc.d = make_dims(g.nx, g.ny, g.nz);
+      cls.push_back(fc);
+    }
+    cls[c].ids.push_back(i);
+    cls[c].ncoef = std::max(cls[c].ncoef, desc->materials[i].n_phases);
+  }
+  DevBuffers mem;
+  int* flag = nullptr;
+  HIP_TRY(mem.alloc(&flag, sizeof(int)));
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+  bool persistent = o.batch_launch == FE_BATCH_PERSISTENT && cls.size() <= (size_t)kBatchClasses;
+  for (F32Class& c : cls) {
+    const int n = (int)c.ids.size();
+    const long long N = c.d.N;
+    persistent = persistent && batch_length_ok(c.d.nx) && batch_length_ok(c.d.ny) && batch_length_ok(c.d.nz);
+    c.bu = div_partial_count(c.d);
+    HIP_TRY(mem.alloc(&c.eps, (size_t)n * 6 * N * sizeof(float)));
+    HIP_TRY(mem.alloc(&c.phase, (size_t)n * N));
+    HIP_TRY(mem.alloc(&c.coef64, (size_t)n * c.ncoef * sizeof(PhaseCoef<double>)));
+    HIP_TRY(mem.alloc(&c.partials, (size_t)n * c.bu * 7 * sizeof(double)));
+    HIP_TRY(mem.alloc(&c.act, (size_t)n * sizeof(int)));
+    std::vector<PhaseCoef<double>> c64((size_t)n * c.ncoef);
+    for (int j = 0; j < n; ++j) {
+      const int i = c.ids[j];
+      const fe_materials& m = desc->materials[i];
+      const RefMedium ref = reference_medium(o, accel ? FE_ACCELERATED : FE_DIRECT, m);
+      std::vector<PhaseCoef<double>> pc = phase_coefs(m, ref);
+      for (int q = 0; q < m.n_phases; ++q) c64[(size_t)j * c.ncoef + q] = pc[q];
+      HIP_TRY(hipMemcpyAsync(c.phase + (size_t)j * N, desc->phase[i], N, hipMemcpyDeviceToDevice, s));
+      Launch<float>::check_phase(c.phase + (size_t)j * N, N, m.n_phases, flag, s);
+    }
+    HIP_TRY(hipMemcpyAsync(c.coef64, c64.data(), c64.size() * sizeof(PhaseCoef<double>), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  int hflag = 0;
+  HIP_TRY(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (hflag) return fail(FE_ERR_INVALID_ARG, "a phase map holds a label >= its n_phases");
+  const int grid = persistent ? batch_persistent_grid(op, accel) : 0;
+  if (persistent && grid <= 0) return fail(FE_ERR_UNSUPPORTED, "cooperative launches are not available");
+
+  // the float32 iteration; iterates into cls[c].eps
+  double sec32 = 0.0;
+  if (persistent) {
+    fe_status ps = run_persistent(op, accel, o, desc, tol, cls, grid, mem, results, &sec32);
+    if (ps != FE_OK) return ps;
+  } else {
+    std::vector<void*> slot(ns);
+    for (const F32Class& c : cls)
+      for (size_t j = 0; j < c.ids.size(); ++j) slot[c.ids[j]] = c.eps + j * 6 * c.d.N;
+    fe_batch_desc sd = *desc;
+    sd.strain = slot.data();
+    const fe_status st32 = solve_batched_impl<float>(op, accel, o, &sd, tol, results, &sec32);
+    if (st32 < 0) return st32;
+  }
+  if (seconds) *seconds = sec32;
+
+  // float64 verification of the float32 strains
   double* red = nullptr;
-  HIP_TRY(mem.alloc(&red, (size_t)std::max(first, 1) * 8 * sizeof(double)));
-  auto verify = [&](size_t c, std::vector<double>& out) -> fe_status {
-    const BatchClassDev& C = hb.cls[c];
-    const Batch bt{C.act, C.ncoef};
-    std::vector<int> all(C.n);
-    for (int j = 0; j < C.n; ++j) all[j] = j;
-    HIP_TRY(hipMemcpyAsync(C.act, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    const int nb = launch_div64<float>(C.eps[0], C.phase, coef64[c], nullptr, nullptr, C.partials, C.d, op, s, bt, C.n);
-    launch_reduce(C.partials, nb, 7, red, s, C.act, C.n);
-    std::vector<double> h((size_t)C.n * 8);
+  HIP_TRY(mem.alloc(&red, (size_t)std::max(ns, 1) * 8 * sizeof(double)));
+  auto verify = [&](F32Class& c, std::vector<double>& out) -> fe_status {
+    const int n = (int)c.ids.size();
+    const Batch bt{c.act, c.ncoef};
+    std::vector<int> all(n);
+    for (int j = 0; j < n; ++j) all[j] = j;
+    HIP_TRY(hipMemcpyAsync(c.act, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    const int nb = launch_div64<float>(c.eps, c.phase, c.coef64, nullptr, nullptr, c.partials, c.d, op, s, bt, n);
+    launch_reduce(c.partials, nb, 7, red, s, c.act, n);
+    std::vector<double> h((size_t)n * 8);
     HIP_TRY(hipMemcpyAsync(h.data(), red, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    out.resize(C.n);
-    for (int j = 0; j < C.n; ++j) {
+    out.resize(n);
+    for (int j = 0; j < n; ++j) {
       double mean[6];
-      for (int q = 0; q < 6; ++q) mean[q] = h[8 * j + 1 + q] / (double)C.d.N;
-      out[j] = std::sqrt(h[8 * j] / (double)C.d.N) / frob(mean);
+      for (int q = 0; q < 6; ++q) mean[q] = h[8 * j + 1 + q] / (double)c.d.N;
+      out[j] = std::sqrt(h[8 * j] / (double)c.d.N) / frob(mean);
     }
     return FE_OK;
   };
   // samples whose float32 strain does not verify: float64 iterations from it
-  std::vector<int> redo;
+  std::vector<std::pair<int, int>> redo;  // (class, index in class)
   for (size_t c = 0; c < cls.size(); ++c) {
     std::vector<double> ev;
-    fe_status vs = verify(c, ev);
+    fe_status vs = verify(cls[c], ev);
     if (vs != FE_OK) return vs;
-    for (int j = 0; j < hb.cls[c].n; ++j) {
+    for (size_t j = 0; j < cls[c].ids.size(); ++j) {
       fe_batch_result& r = results[cls[c].ids[j]];
       r.eta_verify_fp64 = ev[j];
       if (o.refine && r.status != FE_DIVERGED && !(ev[j] <= tol) && r.iterations < o.max_iter)
-        redo.push_back((int)((c << 20) | j));
+        redo.emplace_back((int)c, (int)j);
     }
   }
   if (!redo.empty()) {
@@ -2072,16 +2124,16 @@ fe_status solve_batched_persistent(int op, bool accel, const fe_plan_options& o,
     std::vector<const float*> init(nr);
     std::vector<fe_batch_result> sub(nr);
     for (int k = 0; k < nr; ++k) {
-      const size_t c = (size_t)(redo[k] >> 20);
-      const int j = redo[k] & ((1 << 20) - 1), i = cls[c].ids[j];
+      const F32Class& c = cls[redo[k].first];
+      const int j = redo[k].second, i = c.ids[j];
       grids[k] = desc->grids[i];
       phases[k] = desc->phase[i];
       mats[k] = desc->materials[i];
       for (int q = 0; q < 6; ++q) macro[6 * k + q] = desc->macro_strain[6 * i + q];
       double* o64 = nullptr;
-      HIP_TRY(mem.alloc(&o64, (size_t)6 * hb.cls[c].d.N * sizeof(double)));
+      HIP_TRY(mem.alloc(&o64, (size_t)6 * c.d.N * sizeof(double)));
       out64[k] = o64;
-      init[k] = hb.cls[c].eps[0] + (size_t)j * 6 * hb.cls[c].d.N;
+      init[k] = c.eps + (size_t)j * 6 * c.d.N;
     }
     fe_batch_desc sd;
     sd.n_samples = nr;
@@ -2097,36 +2149,33 @@ fe_status solve_batched_persistent(int op, bool accel, const fe_plan_options& o,
     if (st64 < 0) return st64;
     if (seconds) *seconds += sec64;
     for (int k = 0; k < nr; ++k) {
-      const size_t c = (size_t)(redo[k] >> 20);
-      const int j = redo[k] & ((1 << 20) - 1);
-      const long long N = hb.cls[c].d.N;
-      Launch<float>::convert_to(hb.cls[c].eps[0] + (size_t)j * 6 * N, out64[k], 1, 6 * N, s);
-      fe_batch_result& r = results[cls[c].ids[j]];
+      const F32Class& c = cls[redo[k].first];
+      const int j = redo[k].second;
+      Launch<float>::convert_to(c.eps + (size_t)j * 6 * c.d.N, out64[k], 1, 6 * c.d.N, s);
+      fe_batch_result& r = results[c.ids[j]];
       r.iterations += sub[k].iterations;
       r.eta = sub[k].eta;
       for (int q = 0; q < 6; ++q) r.mean_stress[q] = sub[k].mean_stress[q];
       r.status = sub[k].status;
     }
-    for (size_t c = 0; c < cls.size(); ++c) {  // the returned float32 strains, verified again
+    for (F32Class& c : cls) {  // the returned float32 strains, verified again
       std::vector<double> ev;
       fe_status vs = verify(c, ev);
       if (vs != FE_OK) return vs;
-      for (int j = 0; j < hb.cls[c].n; ++j) {
-        fe_batch_result& r = results[cls[c].ids[j]];
+      for (size_t j = 0; j < c.ids.size(); ++j) {
+        fe_batch_result& r = results[c.ids[j]];
         r.eta_verify_fp64 = ev[j];
         if (r.status == FE_OK && !(ev[j] <= tol)) r.status = FE_NOT_CONVERGED;  // float32 storage floor
       }
     }
   }
-  for (size_t c = 0; c < cls.size(); ++c) {
-    const long long N = hb.cls[c].d.N;
-    for (int j = 0; j < hb.cls[c].n; ++j) {
-      const int i = cls[c].ids[j];
+  for (const F32Class& c : cls)
+    for (size_t j = 0; j < c.ids.size(); ++j) {
+      const int i = c.ids[j];
       if (desc->strain && desc->strain[i])
-        HIP_TRY(hipMemcpyAsync(desc->strain[i], hb.cls[c].eps[0] + (size_t)j * 6 * N, 6 * N * sizeof(float),
+        HIP_TRY(hipMemcpyAsync(desc->strain[i], c.eps + j * 6 * c.d.N, 6 * c.d.N * sizeof(float),
                                hipMemcpyDeviceToDevice, s));
     }
-  }
   HIP_TRY(hipStreamSynchronize(s));
   fe_status worst = FE_OK;
   for (int i = 0; i < ns; ++i)
@@ -2176,10 +2225,12 @@ extern "C" fe_status fe_solve_batched(fe_discretization disc, fe_scheme scheme, 
       if (!std::isfinite(desc->macro_strain[6 * i + q])) return fail(FE_ERR_INVALID_ARG, "sample %d: macro strain", i);
   }
   const int op = disc == FE_GREEN_WP ? OP_WP : OP_ROT;
-  if (o.precision == FE_FP64) return solve_batched_impl<double>(op, scheme == FE_ACCELERATED, o, desc, tol, results, seconds);
-  bool handled = false;
-  const fe_status ps =
-      solve_batched_persistent(op, scheme == FE_ACCELERATED, o, desc, tol, results, seconds, &handled);
-  if (handled) return ps;
-  return solve_batched_impl<float>(op, scheme == FE_ACCELERATED, o, desc, tol, results, seconds);
+  if (o.batch_launch != FE_BATCH_PER_PASS && o.batch_launch != FE_BATCH_PERSISTENT)
+    return fail(FE_ERR_INVALID_ARG, "unknown batch_launch");
+  if (o.precision == FE_FP64) {
+    if (o.batch_launch == FE_BATCH_PERSISTENT)
+      return fail(FE_ERR_UNSUPPORTED, "the persistent batched launch runs float32 fields");
+    return solve_batched_impl<double>(op, scheme == FE_ACCELERATED, o, desc, tol, results, seconds);
+  }
+  return solve_batched_f32(op, scheme == FE_ACCELERATED, o, desc, tol, results, seconds);
 }

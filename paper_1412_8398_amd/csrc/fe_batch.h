@@ -54,7 +54,8 @@ struct BatchDev {
   BatchState* st;
   double tol;
   int max_iter, diverge_window;
-  int* ctrl;  // ctrl[0]: active samples after the last compaction
+  int* ctrl;  // ctrl[0]: active samples after the last compaction; ctrl[1]: a barrier timed out
+  unsigned long long* bar;  // grid barrier counter, zero at the launch
 };
 
 // Workgroups per sample of each pass and the update's z chunk for a grid

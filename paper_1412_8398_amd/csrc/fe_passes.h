@@ -236,8 +236,10 @@ __device__ __forceinline__ bool xline_of(const Dims& d, int line, int& mz, int& 
   return true;
 }
 // One workgroup (line block bx) of the x pass with the Green operator of the
-// displacement form on one sample's spectra S; lds holds 3 LPB LINE values.
-template <typename T, int N, int OP>
+// displacement form on one sample's spectra S; lds holds 3 LPB LINE values,
+// or LPB LINE with SEQ (the components take turns: same arithmetic, a third
+// of the LDS, three times the barriers).
+template <typename T, int N, int OP, bool SEQ = false>
 __device__ __forceinline__ void xgreen3_body(cpx<T>* __restrict__ S, const Dims& d, const cpx<T>* __restrict__ tw,
                                              const WaveTables<T>& wt, const GreenConst<T>& g, cpx<T>* lds, int bx) {
   using C = LineCfg<T, N, 3>;
@@ -253,8 +255,8 @@ __device__ __forceinline__ void xgreen3_body(cpx<T>* __restrict__ S, const Dims&
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int m = 0; m < C::E; ++m) v[c][m] = ok ? base[c * cs + m * C::P] : mk(T(0), T(0));
-  const auto at = [l](int c, int pos) { return (c * C::LPB + l) * C::LINE + pad16(pos); };
-  fft_regs<T, N, C::E, 3, false>(v, t, lds, at, tw);
+  const auto at = [l](int c, int pos) { return ((SEQ ? 0 : c) * C::LPB + l) * C::LINE + pad16(pos); };
+  fft_regs<T, N, C::E, 3, false, SEQ>(v, t, lds, at, tw);
 #pragma unroll
   for (int m = 0; m < C::E; ++m) {
     cpx<T> b[3] = {v[0][m], v[1][m], v[2][m]};
@@ -262,7 +264,7 @@ __device__ __forceinline__ void xgreen3_body(cpx<T>* __restrict__ S, const Dims&
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[c][m] = b[c];
   }
-  fft_regs<T, N, C::E, 3, true>(v, t, lds, at, tw);
+  fft_regs<T, N, C::E, 3, true, SEQ>(v, t, lds, at, tw);
   if (ok) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)

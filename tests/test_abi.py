@@ -128,6 +128,15 @@ def test_batched_solve_rejects_bad_arguments_before_device_work(lib):
     nomat, keep4 = _batch_desc((16, 16, 16))
     keep4[4][0].E[0] = -1.0
     assert call(1, 0, C.byref(nomat), 1e-6) == fe.FE_ERR_INVALID_ARG
+    opt = fe.FePlanOptions()
+    lib.fe_plan_options_default(C.byref(opt))
+    assert opt.batch_launch == 0  # FE_BATCH_PER_PASS
+    opt.batch_launch = 2
+    assert lib.fe_solve_batched(2, 1, C.byref(opt), C.byref(desc), 1e-6, res, None) == fe.FE_ERR_INVALID_ARG
+    assert "batch_launch" in fe.last_error()
+    opt.batch_launch = 1
+    opt.precision = 0  # float64: per-pass launches only
+    assert lib.fe_solve_batched(2, 1, C.byref(opt), C.byref(desc), 1e-6, res, None) == fe.FE_ERR_UNSUPPORTED
 
 
 def test_ctypes_structures_match_the_c_headers(tmp_path):

@@ -2,8 +2,9 @@
 
 Each sample of a batch must follow exactly the iteration a single-sample
 fe_solve of the same plan options performs (same kernels, same constants,
-same fixed-order reductions): iteration counts, eta and the strain field are
-compared bit for bit against single solves with refinement off.  One float64
+same fixed-order reductions), with either float32 launch (one per pass, or
+one cooperative persistent launch): iteration counts, eta and the strain
+field are compared bit for bit against single solves with refinement off.  One float64
 sample is also compared with the oracle at its converged iteration count
 (relative L2 <= 1e-12, the single-solve float64 bar).
 """
@@ -51,7 +52,7 @@ def _single(phase, E, nu, macro, op, scheme, precision, tol, max_iter):
     return r, eps.cpu().numpy()
 
 
-def _batched(specs, op, scheme, precision, tol, max_iter):
+def _batched(specs, op, scheme, precision, tol, max_iter, launch="per_pass"):
     dt = torch.float64 if precision == "fp64" else torch.float32
     samples, outs = [], []
     for ph, E, nu, macro in specs:
@@ -60,20 +61,23 @@ def _batched(specs, op, scheme, precision, tol, max_iter):
         outs.append(eps)
         samples.append(fe.BatchSampleSpec(_dev(ph), E, nu, macro, eps))
     res, status, sec = fe.solve_batched(samples, tol, green=op, scheme=scheme, precision=precision,
-                                        max_iter=max_iter)
+                                        max_iter=max_iter, launch=launch)
     torch.cuda.synchronize()
     return res, status, sec, [e.cpu().numpy() for e in outs]
 
 
-@pytest.mark.parametrize("op,scheme,precision,tol", [
-    ("R", "AS", "fp32", 1e-5),
-    ("W", "DS", "fp32", 1e-3),  # float32 DS at contrast 100 stalls near 1.4e-4 (float32 tau)
-    ("R", "DS", "fp64", 1e-8),
-    ("W", "AS", "fp64", 1e-9),
+@pytest.mark.parametrize("op,scheme,precision,tol,launch", [
+    ("R", "AS", "fp32", 1e-5, "per_pass"),
+    ("R", "AS", "fp32", 1e-5, "persistent"),
+    ("W", "DS", "fp32", 1e-3, "per_pass"),  # float32 DS at contrast 100 stalls near 1.4e-4 (float32 tau)
+    ("W", "DS", "fp32", 1e-3, "persistent"),
+    ("R", "DS", "fp64", 1e-8, "per_pass"),
+    ("W", "AS", "fp64", 1e-9, "per_pass"),
 ])
-def test_batched_samples_match_single_solves_bitwise(op, scheme, precision, tol):
+def test_batched_samples_match_single_solves_bitwise(op, scheme, precision, tol, launch):
+    """Both float32 launches (one per pass, one persistent) and float64."""
     specs = _samples()
-    res, status, sec, eps = _batched(specs, op, scheme, precision, tol, 3000)
+    res, status, sec, eps = _batched(specs, op, scheme, precision, tol, 3000, launch)
     assert status == fe.FE_OK, [(r.status, r.iterations, r.eta) for r in res]
     assert sec > 0
     its = []
@@ -135,19 +139,21 @@ def test_batched_rejects_bad_labels():
 
 
 def test_batch_outside_the_persistent_lengths_matches_single_solves():
-    """A batch with a grid length the persistent kernel is not built for (8)
-    runs one launch per pass; samples still equal single solves bit for bit."""
+    """A persistent batch with a grid length the persistent kernel is not
+    built for (8) runs one launch per pass; samples still equal single solves
+    bit for bit."""
     a, _ = boolean_spheres((8, 16, 16), 2.0, 0.2, 21)
     b, _ = boolean_spheres((16, 16, 16), 3.0, 0.25, 22)
     specs = [(a, [1.0, 10.0], [0.3, 0.3], [0, 0, 0, 0, 0, 1.0]), (b, [1.0, 5.0], [0.3, 0.3], [1.0, 0, 0, 0, 0, 0])]
-    res, status, _, eps = _batched(specs, "R", "AS", "fp32", 1e-5, 2000)
+    res, status, _, eps = _batched(specs, "R", "AS", "fp32", 1e-5, 2000, "persistent")
     assert status == fe.FE_OK
     for (ph, E, nu, macro), rb, eb in zip(specs, res, eps):
         rs, es = _single(ph, E, nu, macro, "R", "AS", "fp32", 1e-5, 2000)
         assert rb.iterations == rs.iterations and rb.eta == rs.eta and np.array_equal(eb, es)
 
 
-def test_float64_continuation_reaches_the_tolerance():
+@pytest.mark.parametrize("launch", ["per_pass", "persistent"])
+def test_float64_continuation_reaches_the_tolerance(launch):
     """High-contrast samples whose float32 iteration stalls above 1e-6 (the
     float32 floor) continue in float64 from their float32 iterate: every
     returned strain verifies to 1e-6 in float64, and without the
@@ -156,8 +162,8 @@ def test_float64_continuation_reaches_the_tolerance():
 
     samples = [s for s in batch_samples(24, 7001, sizes=(32, 48))]
     specs = [(s.phase, [1.0, s.contrast], [s.nu, s.nu], s.macro_strain) for s in samples]
-    plain, _, _, _ = _batched_opts(specs, "R", "AS", 1e-6, 2000, refine=False)
-    res, status, _, eps = _batched_opts(specs, "R", "AS", 1e-6, 2000, refine=True)
+    plain, _, _, _ = _batched_opts(specs, "R", "AS", 1e-6, 2000, refine=False, launch=launch)
+    res, status, _, eps = _batched_opts(specs, "R", "AS", 1e-6, 2000, refine=True, launch=launch)
     assert status == fe.FE_OK, [(r.status, r.iterations, r.eta_verify_fp64) for r in res]
     assert all(r.eta_verify_fp64 <= 1e-6 for r in res)
     assert any(r.eta_verify_fp64 > 1e-6 for r in plain)
@@ -165,7 +171,7 @@ def test_float64_continuation_reaches_the_tolerance():
         assert rr.iterations >= rp.iterations and np.isfinite(e).all()
 
 
-def _batched_opts(specs, op, scheme, tol, max_iter, refine):
+def _batched_opts(specs, op, scheme, tol, max_iter, refine, launch="per_pass"):
     samples, outs = [], []
     for ph, E, nu, macro in specs:
         nz, ny, nx = ph.shape
@@ -173,6 +179,6 @@ def _batched_opts(specs, op, scheme, tol, max_iter, refine):
         outs.append(eps)
         samples.append(fe.BatchSampleSpec(_dev(ph), E, nu, macro, eps))
     res, status, sec = fe.solve_batched(samples, tol, green=op, scheme=scheme, precision="fp32", max_iter=max_iter,
-                                        refine=refine, raise_on_error=False)
+                                        refine=refine, raise_on_error=False, launch=launch)
     torch.cuda.synchronize()
     return res, status, sec, [e.cpu().numpy() for e in outs]
