@@ -63,7 +63,9 @@ def pass_bytes(L: int, elem: int = 4):
     }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ASR_fp32_512.json")
+def traffic_file(L: int) -> str:
+    """The committed per-pass traffic record of an L^3 run (paper_1412_8398_amd.traffic)."""
+    return os.path.join(ROOT, "profiles", f"traffic_ASR_fp32_{L}.json")
 
 
 def measured_traffic(pass_name: str, L: int):
@@ -72,9 +74,9 @@ def measured_traffic(pass_name: str, L: int):
     counters were taken on another grid or the kernel's sources changed since."""
     import hashlib
 
-    if L != 512 or not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(traffic_file(L)):
         return None
-    with open(TRAFFIC_FILE) as fh:
+    with open(traffic_file(L)) as fh:
         rec = json.load(fh).get("kernels", {}).get(pass_name)
     if rec is None:
         return None

@@ -43,7 +43,9 @@ enum { BP_DIV = 0, BP_ZR2C, BP_YFWD, BP_XGREEN, BP_YINV, BP_ZC2R, BP_UPDATE };
 // take turns through the buffer; at most 26 KiB).
 template <int N>
 constexpr size_t batch_lds_of() {
-  constexpr size_t z = (size_t)N * StridedCfg<float, N>::TX, y = (size_t)N * StridedCfg<float, N, true>::TX;
+  using Z = StridedCfg<float, N>;
+  using Y = StridedCfg<float, N, true>;
+  constexpr size_t z = (size_t)Z::ROWS * Z::TX, y = (size_t)Y::ROWS * Y::TX;
   constexpr size_t x = (size_t)LineCfg<float, N, 3>::LPB * LineCfg<float, N, 3>::LINE;
   return sizeof(cpx<float>) * (z > y ? (z > x ? z : x) : (y > x ? y : x));
 }

@@ -30,6 +30,13 @@ struct StridedCfg {
   static constexpr bool BIG = YPASS && N >= 768;
   static constexpr int TX = imax(1, imin((BIG ? 512 : 256) / P, (BIG ? 2 : 1) * lds_budget<T>() / N));
   static constexpr int NT = TX * P;
+  // LDS rows of TX complex values; with TX <= 16 (lengths >= 384) one empty
+  // row follows every 16, so that the two rows a 16-lane quarter of a wave
+  // touches in an exchange fall on different halves of the 32 banks (rows
+  // 16 or 32 positions apart would otherwise share them)
+  static constexpr int RPAD = TX <= 16 ? 16 : 0;
+  static constexpr int ROWS = N + (RPAD ? N / RPAD : 0);
+  static __device__ __forceinline__ int row(int pos) { return RPAD ? pos + pos / RPAD : pos; }
 };
 
 // x passes: LPB lines per workgroup, P = N/E threads per line.
@@ -39,10 +46,14 @@ struct LineCfg {
   static constexpr int P = N / E;
   static constexpr int LPB = imax(1, 256 / P);
   static constexpr int NT = LPB * P;
-  static constexpr int LINE = N + N / 16;  // LDS line pitch: one pad per 16 elements
+  // LDS position of element pos of a line: lines of 128 and more permute
+  // each aligned block of 32 by an XOR with bits 3-7 of pos (no padding; the
+  // strided writes of every exchange stage then spread over all 32 banks
+  // within each 16-lane quarter wave), shorter lines pad one element per 16
+  static constexpr bool SWZ = N >= 128;
+  static constexpr int LINE = SWZ ? N : N + N / 16;
+  static __device__ __forceinline__ int pos(int p) { return SWZ ? p ^ ((p >> 3) & 31) : p + (p >> 4); }
 };
-
-__device__ __forceinline__ int pad16(int pos) { return pos + (pos >> 4); }
 
 template <typename T>
 struct alignas(4 * sizeof(T)) cpx2 {
@@ -70,7 +81,7 @@ __device__ __forceinline__ void ypass_body(cpx<T>* __restrict__ S, const Dims& d
   cpx<T> v[1][C::E];
 #pragma unroll
   for (int m = 0; m < C::E; ++m) v[0][m] = ok ? base[(long long)(t + m * C::P) * ys] : mk(T(0), T(0));
-  fft_regs<T, N, C::E, 1, INV>(v, t, lds, [col](int, int pos) { return pos * C::TX + col; }, tw);
+  fft_regs<T, N, C::E, 1, INV>(v, t, lds, [col](int, int pos) { return C::row(pos) * C::TX + col; }, tw);
   if (ok) {
 #pragma unroll
     for (int m = 0; m < C::E; ++m) base[(long long)(t + m * C::P) * ys] = v[0][m];
@@ -82,7 +93,7 @@ __global__ __launch_bounds__((StridedCfg<T, N, true>::NT)) void k_ypass(cpx<T>* 
                                                                       const cpx<T>* __restrict__ tw, Batch bt) {
   using C = StridedCfg<T, N, true>;
   if (bt.active) S += (long long)bt.active[blockIdx.y] * (gridDim.x / (((d.nx + C::TX - 1) / C::TX) * d.H)) * spec_size(d);
-  __shared__ cpx<T> lds[N * C::TX];
+  __shared__ cpx<T> lds[C::ROWS * C::TX];
   // x-neighbour tiles share 128-byte lines: same L2
   ypass_body<T, N, INV>(S, d, tw, lds, xcd_block(blockIdx.x, gridDim.x));
 }
@@ -112,9 +123,9 @@ __device__ __forceinline__ void zr2c_body(const T* __restrict__ R, cpx<T>* __res
 #pragma unroll
   for (int m = 0; m < C::E; ++m)
     v[0][m] = ok ? *reinterpret_cast<const cpx<T>*>(src + zrow(d, t + m * C::P, y) * d.nx) : mk(T(0), T(0));
-  fft_regs<T, N, C::E, 1, false>(v, t, lds, [col](int, int pos) { return pos * C::TX + col; }, tw);
+  fft_regs<T, N, C::E, 1, false>(v, t, lds, [col](int, int pos) { return C::row(pos) * C::TX + col; }, tw);
 #pragma unroll
-  for (int m = 0; m < C::E; ++m) lds[(t + m * C::P) * C::TX + col] = v[0][m];
+  for (int m = 0; m < C::E; ++m) lds[C::row(t + m * C::P) * C::TX + col] = v[0][m];
   __syncthreads();
   cpx<T>* dst = S + (long long)c * spec_size(d) + 2 * (ok ? pp : 0);
   constexpr int H = N / 2 + 1, NS = (H + C::P - 1) / C::P;
@@ -122,8 +133,8 @@ __device__ __forceinline__ void zr2c_body(const T* __restrict__ R, cpx<T>* __res
   for (int i = 0; i < NS; ++i) {
     const int mz = t + i * C::P;
     if (mz >= H) break;
-    const cpx<T> Z = lds[mz * C::TX + col];
-    const cpx<T> Zm = conj(lds[((N - mz) % N) * C::TX + col]);
+    const cpx<T> Z = lds[C::row(mz) * C::TX + col];
+    const cpx<T> Zm = conj(lds[C::row((N - mz) % N) * C::TX + col]);
     const cpx<T> Dd = sub(Z, Zm);
     cpx2<T> o;
     o.a = scale(add(Z, Zm), T(0.5));
@@ -143,7 +154,7 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zr2c(const T* __rest
     R += smp * nc * d.N;
     S += smp * nc * spec_size(d);
   }
-  __shared__ cpx<T> lds[N * C::TX];
+  __shared__ cpx<T> lds[C::ROWS * C::TX];
   // x-neighbour tiles share 128-byte lines: same L2
   zr2c_body<T, N>(R, S, d, tw, lds, xcd_block(blockIdx.x, gridDim.x));
 }
@@ -183,16 +194,16 @@ __device__ __forceinline__ void zc2r_body(const cpx<T>* __restrict__ S, T* __res
     const int mz = t + i * C::P;
     if (mz < H) {
       const cpx<T> A = ab[i].a, B = ab[i].b;
-      lds[mz * C::TX + col] = mk(A.re - B.im, A.im + B.re);
-      if (mz > 0 && 2 * mz < N) lds[(N - mz) * C::TX + col] = mk(A.re + B.im, B.re - A.im);
+      lds[C::row(mz) * C::TX + col] = mk(A.re - B.im, A.im + B.re);
+      if (mz > 0 && 2 * mz < N) lds[C::row(N - mz) * C::TX + col] = mk(A.re + B.im, B.re - A.im);
     }
   }
   __syncthreads();
   cpx<T> v[1][C::E];
 #pragma unroll
-  for (int m = 0; m < C::E; ++m) v[0][m] = lds[(t + m * C::P) * C::TX + col];
+  for (int m = 0; m < C::E; ++m) v[0][m] = lds[C::row(t + m * C::P) * C::TX + col];
   __syncthreads();
-  fft_regs<T, N, C::E, 1, true>(v, t, lds, [col](int, int pos) { return pos * C::TX + col; }, tw);
+  fft_regs<T, N, C::E, 1, true>(v, t, lds, [col](int, int pos) { return C::row(pos) * C::TX + col; }, tw);
   if (ok) {
     T* dst = R + (long long)c * d.N + 2 * pp;
 #pragma unroll
@@ -211,7 +222,7 @@ __global__ __launch_bounds__((StridedCfg<T, N>::NT)) void k_zc2r(const cpx<T>* _
     R += smp * nc * d.N;
     S += smp * nc * spec_size(d);
   }
-  __shared__ cpx<T> lds[N * C::TX];
+  __shared__ cpx<T> lds[C::ROWS * C::TX];
   // x-neighbour tiles share 128-byte lines: same L2
   zc2r_body<T, N>(S, R, d, tw, lds, xcd_block(blockIdx.x, gridDim.x));
 }
@@ -255,7 +266,7 @@ __device__ __forceinline__ void xgreen3_body(cpx<T>* __restrict__ S, const Dims&
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int m = 0; m < C::E; ++m) v[c][m] = ok ? base[c * cs + m * C::P] : mk(T(0), T(0));
-  const auto at = [l](int c, int pos) { return ((SEQ ? 0 : c) * C::LPB + l) * C::LINE + pad16(pos); };
+  const auto at = [l](int c, int pos) { return ((SEQ ? 0 : c) * C::LPB + l) * C::LINE + C::pos(pos); };
   fft_regs<T, N, C::E, 3, false, SEQ>(v, t, lds, at, tw);
 #pragma unroll
   for (int m = 0; m < C::E; ++m) {
@@ -309,7 +320,7 @@ __global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xgreen6(cpx<T>* __re
   for (int c = 0; c < 6; ++c)
 #pragma unroll
     for (int m = 0; m < C::E; ++m) v[c][m] = ok ? base[c * cs + m * C::P] : mk(T(0), T(0));
-  const auto at = [l](int, int pos) { return l * C::LINE + pad16(pos); };
+  const auto at = [l](int, int pos) { return l * C::LINE + C::pos(pos); };
   fft_regs<T, N, C::E, 6, false, true>(v, t, lds, at, tw);
 #pragma unroll
   for (int m = 0; m < C::E; ++m) {
@@ -360,7 +371,7 @@ __global__ __launch_bounds__((LineCfg<T, N, 6>::NT)) void k_xeta6(const cpx<T>* 
   for (int c = 0; c < 6; ++c)
 #pragma unroll
     for (int m = 0; m < C::E; ++m) v[c][m] = ok ? src[c * cs + m * C::P] : mk(T(0), T(0));
-  const auto at = [l](int, int pos) { return l * C::LINE + pad16(pos); };
+  const auto at = [l](int, int pos) { return l * C::LINE + C::pos(pos); };
   fft_regs<T, N, C::E, 6, false, true>(v, t, lds, at, tw);
   const long long bs = 3 * cs;  // B follows A
   cpx<TS>* bl = base + (long long)(ok ? line : 0) * N + t;
