@@ -6,6 +6,14 @@ equilibrium tolerance; the learned run starts from the network's prediction
 and its time includes the prediction.
 
     python -m paper_1412_8398_amd.warmstart --weights w.npy --size 128 --count 16
+
+Break-even model, per cell.  The scheme contracts the error of its iterate by
+a factor rho per iteration (measured: rho = (eta_end / eta_0)^(1/k) of the
+plain run), so a start whose error is e times that of eps_bar (e: the
+prediction's relative L2 distance to the converged strain, against the
+fluctuation eps - eps_bar) saves about log(e) / log(rho) iterations.  The
+prediction costs C = t_predict / t_iteration iterations, so the learned start
+pays only if e < rho^C (e_breakeven).
 """
 from __future__ import annotations
 
@@ -59,6 +67,11 @@ def compare_one(net, phase, E, nu, macro, tol=1e-6, max_iter=3000, plan=None):
     fluct = torch.linalg.vector_norm((eps_p - mac).double()).item()
     pred_err = torch.linalg.vector_norm((pred[0] - eps_p).double()).item() / max(fluct, 1e-300)
     sp, sl = np.asarray(rp.mean_stress), np.asarray(rl.mean_stress)
+    hist = np.asarray(rp.eta_history, dtype=np.float64)
+    k = max(int(rp.iterations), 1)
+    rho = float((rp.eta_verify_fp64 / hist[0]) ** (1.0 / k)) if hist.size and hist[0] > 0 else float("nan")
+    t_iter = (t1 - t0) / k
+    cost = t_pred / t_iter
     out = {
         "plain": {"iterations": rp.iterations, "seconds": t1 - t0, "eta0": float(rp.eta_history[0]),
                   "eta": rp.eta_verify_fp64, "status": rp.status},
@@ -66,6 +79,12 @@ def compare_one(net, phase, E, nu, macro, tol=1e-6, max_iter=3000, plan=None):
                     "eta0": float(rl.eta_history[0]), "eta": rl.eta_verify_fp64, "status": rl.status},
         "prediction_rel_l2": pred_err,
         "mean_stress_rel_diff": float(np.linalg.norm(sl - sp) / max(np.linalg.norm(sp), 1e-300)),
+        "rho": rho,
+        "iteration_seconds": t_iter,
+        "prediction_cost_iterations": cost,
+        "iterations_saved": int(rp.iterations) - int(rl.iterations),
+        "iterations_saved_model": float(np.log(pred_err) / np.log(rho)) if 0 < rho < 1 else float("nan"),
+        "e_breakeven": float(rho ** cost) if 0 < rho < 1 else float("nan"),
     }
     if own:
         plan.close()
@@ -112,7 +131,13 @@ def main(argv=None):
             "prediction_rel_l2_median": float(np.median([r["prediction_rel_l2"] for r in rows])),
             "eta0_plain_median": float(np.median([r["plain"]["eta0"] for r in rows])),
             "eta0_learned_median": float(np.median([r["learned"]["eta0"] for r in rows])),
-            "mean_stress_rel_diff_max": float(max(r["mean_stress_rel_diff"] for r in rows))}
+            "mean_stress_rel_diff_max": float(max(r["mean_stress_rel_diff"] for r in rows)),
+            "speedup": float(t_p.sum() / t_l.sum()),
+            "rho_median": float(np.median([r["rho"] for r in rows])),
+            "prediction_cost_iterations_median": float(np.median([r["prediction_cost_iterations"] for r in rows])),
+            "iterations_saved_mean": float(np.mean([r["iterations_saved"] for r in rows])),
+            "iterations_saved_model_mean": float(np.mean([r["iterations_saved_model"] for r in rows])),
+            "e_breakeven_median": float(np.median([r["e_breakeven"] for r in rows]))}
     print(json.dumps({"summary": summ}), flush=True)
     if args.out:
         with open(args.out, "w") as fh:

@@ -1,8 +1,11 @@
 """The trained warm-start network (paper_1412_8398_amd/weights) on held-out
 cells of its training distribution: its prediction is closer to the
 converged strain than the plain start eps^0 = eps_bar (relative L2 1 by
-definition), the solve from it reaches the same equilibrium, and the result
-records what it gains in iterations."""
+definition), the solve from it reaches the same equilibrium, and it saves
+iterations, no more than the contraction model allows: a start whose error
+is e times that of eps_bar saves at most about log(e) / log(rho) iterations
+(rho: the plain run's contraction per iteration).  Measured on 16 cells at
+512^3: 0.94 iterations saved per cell against a prediction that costs 7.2."""
 import os
 
 import numpy as np
@@ -34,7 +37,10 @@ def test_learned_start_is_closer_and_converges_to_the_same_answer():
         assert r["plain"]["status"] == fe.FE_OK and r["learned"]["status"] == fe.FE_OK
         assert r["mean_stress_rel_diff"] <= 1e-5
     err = np.array([r["prediction_rel_l2"] for r in rows])
-    assert np.median(err) < 0.8, err
+    assert np.median(err) < 0.6, err
     it_p = sum(r["plain"]["iterations"] for r in rows)
     it_l = sum(r["learned"]["iterations"] for r in rows)
-    assert it_l <= it_p + len(rows), (it_p, it_l)  # never worse than one iteration per cell on average
+    assert it_l < it_p, (it_p, it_l)  # the gain: fewer iterations in total
+    saved = sum(r["iterations_saved"] for r in rows)
+    bound = sum(max(r["iterations_saved_model"], 0.0) + 1.0 for r in rows)
+    assert saved <= bound, (saved, bound)
