@@ -1739,7 +1739,7 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
         out.eta = eta;
         for (int q = 0; q < 6; ++q) out.mean_stress[q] = mean[q];
         bool done = true;
-        // same stopping order as the single-sample solve
+        // same stopping order as the single-sample solve with refinement off
         if (!std::isfinite(eta)) {
           out.status = FE_DIVERGED;
         } else if (eta <= tol) {
@@ -2162,13 +2162,15 @@ fe_status solve_batched_f32(int op, bool accel, const fe_plan_options& o, const 
       std::vector<double> ev;
       fe_status vs = verify(c, ev);
       if (vs != FE_OK) return vs;
-      for (size_t j = 0; j < c.ids.size(); ++j) {
-        fe_batch_result& r = results[c.ids[j]];
-        r.eta_verify_fp64 = ev[j];
-        if (r.status == FE_OK && !(ev[j] <= tol)) r.status = FE_NOT_CONVERGED;  // float32 storage floor
-      }
+      for (size_t j = 0; j < c.ids.size(); ++j) results[c.ids[j]].eta_verify_fp64 = ev[j];
     }
   }
+  // with refinement FE_OK means the returned float32 strain verifies to tol
+  // (a sample that cannot continue, or ends at the float32 storage floor of
+  // its rounded strain, is FE_NOT_CONVERGED)
+  if (o.refine)
+    for (int i = 0; i < ns; ++i)
+      if (results[i].status == FE_OK && !(results[i].eta_verify_fp64 <= tol)) results[i].status = FE_NOT_CONVERGED;
   for (const F32Class& c : cls)
     for (size_t j = 0; j < c.ids.size(); ++j) {
       const int i = c.ids[j];
