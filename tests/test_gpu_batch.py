@@ -182,3 +182,33 @@ def _batched_opts(specs, op, scheme, tol, max_iter, refine, launch="per_pass"):
                                         refine=refine, raise_on_error=False, launch=launch)
     torch.cuda.synchronize()
     return res, status, sec, [e.cpu().numpy() for e in outs]
+
+
+def test_persistent_launch_with_more_grid_classes_than_it_holds_falls_back():
+    """Nine distinct grids (the persistent kernel holds eight classes): the
+    batch runs one launch per pass, and still equals single solves."""
+    shapes = [(16, 16, 16), (16, 16, 24), (16, 24, 16), (24, 16, 16), (16, 16, 32), (16, 32, 16), (32, 16, 16),
+              (24, 24, 16), (16, 24, 24)]
+    specs = []
+    for i, shp in enumerate(shapes):
+        ph, _ = boolean_spheres(shp, 2.5, 0.2, 40 + i)
+        specs.append((ph, [1.0, 8.0], [0.3, 0.3], [0, 0, 0, 0, 0, 1.0]))
+    res, status, _, eps = _batched(specs, "R", "AS", "fp32", 1e-4, 500, "persistent")
+    assert status == fe.FE_OK
+    for (ph, E, nu, macro), rb, eb in zip(specs, res, eps):
+        rs, es = _single(ph, E, nu, macro, "R", "AS", "fp32", 1e-4, 500)
+        assert rb.iterations == rs.iterations and rb.eta == rs.eta and np.array_equal(eb, es)
+
+
+@pytest.mark.parametrize("max_iter", [0, 3])
+def test_both_launches_agree_at_a_small_iteration_cap(max_iter):
+    """At caps of 0 and 3 iterations every sample ends FE_NOT_CONVERGED at the
+    cap, with the same iterate and eta from either launch."""
+    specs = _samples()
+    a, sa, _, ea = _batched(specs, "R", "AS", "fp32", 1e-12, max_iter, "per_pass")
+    b, sb, _, eb = _batched(specs, "R", "AS", "fp32", 1e-12, max_iter, "persistent")
+    assert sa == sb == fe.FE_NOT_CONVERGED
+    for ra, rb, xa, xb in zip(a, b, ea, eb):
+        assert ra.status == rb.status == fe.FE_NOT_CONVERGED
+        assert ra.iterations == rb.iterations == max_iter
+        assert ra.eta == rb.eta and np.array_equal(xa, xb)
