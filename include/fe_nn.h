@@ -104,6 +104,15 @@ typedef struct {
 /* y = (relu ? max(.,0) : id)(conv3(x, w) + b), y: [..][c_out] */
 fe_status fe_nn_conv3_forward(const fe_nn_conv_shape* s, const uint16_t* x, const float* w, const float* b,
                               int32_t relu, uint16_t* y, void* hip_stream);
+/* A decoder layer on its concatenated input read in place:
+ * y = (relu ? max(.,0) : id)(conv3([up2(coarse), skip], w) + b), where up2 is
+ * the nearest upsampling to s's grid (coarse: [..][nz/2][ny/2][nx/2][c_coarse],
+ * even nx, ny, nz) and skip: [..][c_in - c_coarse].  Equal, bit for bit, to
+ * fe_nn_conv3_forward on the materialised concatenation.  Supported
+ * (c_in, c_out, c_coarse): (48, 16, 32), (96, 32, 64), (192, 64, 128). */
+fe_status fe_nn_conv3_forward_cat(const fe_nn_conv_shape* s, int32_t c_coarse, const uint16_t* coarse,
+                                  const uint16_t* skip, const float* w, const float* b, int32_t relu, uint16_t* y,
+                                  void* hip_stream);
 /* dx = gradient of sum(dy * y) with respect to x for y = conv3(x, w), where dy
  * is first multiplied by (y_mask > 0) when y_mask is not NULL (the relu of a
  * layer whose output is y_mask).  dy, y_mask: [..][c_out]; dx: [..][c_in];

@@ -498,6 +498,8 @@ def _bind_nn(lib):
         getattr(lib, f).restype = C.c_int
     lib.fe_nn_conv3_forward.argtypes = [C.POINTER(FeNNConvShape), P, P, P, C.c_int32, P, P]
     lib.fe_nn_conv3_forward.restype = C.c_int
+    lib.fe_nn_conv3_forward_cat.argtypes = [C.POINTER(FeNNConvShape), C.c_int32, P, P, P, P, C.c_int32, P, P]
+    lib.fe_nn_conv3_forward_cat.restype = C.c_int
     lib.fe_nn_conv3_backward_data.argtypes = [C.POINTER(FeNNConvShape), P, P, P, P, P]
     lib.fe_nn_conv3_backward_data.restype = C.c_int
     lib.fe_nn_conv3_backward_weight.argtypes = [C.POINTER(FeNNConvShape), P, P, P, P, P, P]
@@ -553,6 +555,27 @@ def conv3_forward(x, w, b=None, relu=True, stream=None):
     y = torch.empty(lead + (c_out,), dtype=torch.bfloat16, device=x.device)
     _check(lib.fe_nn_conv3_forward(C.byref(_shape(x, c_in, c_out)), px, pw, pb, 1 if relu else 0, _ptr(y), stream),
            "fe_nn_conv3_forward")
+    return y
+
+
+def conv3_forward_cat(coarse, skip, w, b=None, relu=True, stream=None):
+    """fe_nn_conv3_forward_cat: conv3 of [nearest upsampling of coarse, skip]
+    read in place; coarse (B, nz/2, ny/2, nx/2, c_coarse) and skip
+    (B, nz, ny, nx, c_in - c_coarse) bfloat16 -> y (B, nz, ny, nx, c_out)."""
+    import torch
+    lead, c_skip = _act5(skip, "skip")
+    c_in, c_out = _weights(w)
+    c_coarse = c_in - c_skip
+    B, nz, ny, nx = lead
+    shp = (B, nz // 2, ny // 2, nx // 2, c_coarse)
+    pc, ps, pw, pb = _addresses([("coarse", _checked(coarse, "coarse", torch.bfloat16, shp, required=True)),
+                                 ("skip", _checked(skip, "skip", torch.bfloat16, lead + (c_skip,), required=True)),
+                                 ("w", _checked(w, "w", torch.float32, (27, c_in, c_out), required=True)),
+                                 ("b", _checked(b, "b", torch.float32, (c_out,)))])
+    lib = _bind_nn(load_library())
+    y = torch.empty(lead + (c_out,), dtype=torch.bfloat16, device=skip.device)
+    _check(lib.fe_nn_conv3_forward_cat(C.byref(_shape(skip, c_in, c_out)), c_coarse, pc, ps, pw, pb,
+                                       1 if relu else 0, _ptr(y), stream), "fe_nn_conv3_forward_cat")
     return y
 
 

@@ -72,6 +72,12 @@ __host__ __device__ inline int conv_tiles(const Grid3& g) {
 // elementwise (mask has the input's shape): the masked gradient of a relu.
 void conv3_forward(int cin, int cout, const uint16_t* x, const uint16_t* mask, const uint16_t* wpack,
                    const float* bias, int relu, uint16_t* y, Grid3 g, hipStream_t s);
+// y = act(conv3([up2(coarse), skip], w) + b): the concatenation of the
+// nearest upsampling of coarse (ca channels, grid g halved) and skip
+// (cin - ca channels, grid g), read in place (the decoder layers)
+bool conv_cat_supported(int cin, int cout, int ca);
+void conv3_forward_cat(int cin, int cout, int ca, const uint16_t* coarse, const uint16_t* skip, const uint16_t* wpack,
+                       const float* bias, int relu, uint16_t* y, Grid3 g, hipStream_t s);
 // Per-block partial weight gradients for dw[t][c][o] = sum_v x[v + off(t), c] G[v, o],
 // G = dy * (ymask > 0) (ymask nullable); returns the number of partial sets.
 int conv3_wgrad_partials(int cin, int cout, const uint16_t* x, const uint16_t* dy, const uint16_t* ymask,

@@ -59,10 +59,15 @@ __device__ __forceinline__ TileCoord tile_of(int t, const Grid3& g) {
 // ---------------------------------------------------------------------------
 // forward (and input gradient with flipped, transposed weights)
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, bool RELU, bool MASKED>
+// With CA > 0 the input is the concatenation [nearest upsampling of XC
+// (CA channels on the grid halved in each direction), X (CIN - CA channels)]
+// read in place: a decoder layer without its concatenated input in HBM (the
+// channel chunks never straddle the two sources, CA being a multiple of CCH).
+template <int CIN, int COUT, bool RELU, bool MASKED, int CA = 0>
 __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ M,
                                                const u32x4* __restrict__ W, const float* __restrict__ bias,
-                                               uint16_t* __restrict__ Y, Grid3 g) {
+                                               uint16_t* __restrict__ Y, Grid3 g,
+                                               const uint16_t* __restrict__ XC = nullptr) {
   constexpr int CCH = conv_cch(CIN), NCH = CIN / CCH, TPK = 32 / CCH, KS = conv_ksteps(CIN), MT = COUT / 16;
   constexpr int NG = conv_groups(CIN);
   constexpr int PIECES = CCH / 8;
@@ -80,15 +85,23 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
   // this lane's reduction group: tap slot within the k step and channel piece
   const int slot = (grp * 8) / CCH, pc = ((grp * 8) % CCH) / 8;
 
+  static_assert(CA % CCH == 0 && CA < CIN, "channel chunks within one source");
   for (int ch = 0; ch < NCH; ++ch) {
     if (ch) __syncthreads();
+    const bool from_coarse = CA > 0 && ch * CCH < CA;
     for (int i = threadIdx.x; i < HV * PIECES; i += 256) {
       const int p = i % PIECES, hv = i / PIECES;
       const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
       const int gx = wrapi(tc.x0 - 1 + hx, g.nx), gy = wrapi(tc.y0 - 1 + hy, g.ny), gz = wrapi(tc.z0 - 1 + hz, g.nz);
-      const long long off = (((zb + gz) * g.ny + gy) * g.nx + gx) * CIN + ch * CCH + p * 8;
-      u32x4 v = *reinterpret_cast<const u32x4*>(X + off);
-      if (MASKED) v = mask8(v, *reinterpret_cast<const u32x4*>(M + off));
+      u32x4 v;
+      if (from_coarse) {
+        const long long cv = (((long long)tc.smp * (g.nz / 2) + gz / 2) * (g.ny / 2) + gy / 2) * (g.nx / 2) + gx / 2;
+        v = *reinterpret_cast<const u32x4*>(XC + cv * CA + ch * CCH + p * 8);
+      } else {
+        const long long off = (((zb + gz) * g.ny + gy) * g.nx + gx) * (CIN - CA) + (ch * CCH - CA) + p * 8;
+        v = *reinterpret_cast<const u32x4*>(X + off);
+        if (MASKED) v = mask8(v, *reinterpret_cast<const u32x4*>(M + off));
+      }
       lds[i] = v;
     }
     __syncthreads();
@@ -269,6 +282,34 @@ void conv3_forward(int cin, int cout, const uint16_t* x, const uint16_t* mask, c
   }
   FE_NN_CONV_SHAPES(FE_CASE)
   FE_NN_BWD_SHAPES(FE_CASE)
+#undef FE_CASE
+}
+
+// the decoder layers: (c_in, c_out, coarse channels of c_in)
+#define FE_NN_CAT_SHAPES(X) X(48, 16, 32) X(96, 32, 64) X(192, 64, 128)
+
+bool conv_cat_supported(int cin, int cout, int ca) {
+#define FE_CASE(a, b, c) \
+  if (cin == a && cout == b && ca == c) return true;
+  FE_NN_CAT_SHAPES(FE_CASE)
+#undef FE_CASE
+  return false;
+}
+
+void conv3_forward_cat(int cin, int cout, int ca, const uint16_t* coarse, const uint16_t* skip, const uint16_t* wpack,
+                       const float* bias, int relu, uint16_t* y, Grid3 g, hipStream_t s) {
+  const dim3 grid(conv_tiles(g)), block(256);
+  const u32x4* wp = reinterpret_cast<const u32x4*>(wpack);
+#define FE_CASE(a, b, c)                                                                                          \
+  if (cin == a && cout == b && ca == c) {                                                                         \
+    if (relu)                                                                                                     \
+      hipLaunchKernelGGL((k_conv3<a, b, true, false, c>), grid, block, 0, s, skip, nullptr, wp, bias, y, g, coarse); \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_conv3<a, b, false, false, c>), grid, block, 0, s, skip, nullptr, wp, bias, y, g,      \
+                         coarse);                                                                                 \
+    return;                                                                                                       \
+  }
+  FE_NN_CAT_SHAPES(FE_CASE)
 #undef FE_CASE
 }
 

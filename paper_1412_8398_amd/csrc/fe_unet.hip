@@ -253,9 +253,11 @@ extern "C" fe_status fe_unet_set_params(fe_unet* n, const float* h) {
 // ---------------------------------------------------------------------------
 static fe_status ensure_workspace(fe_unet* n, const Grid3& g, bool grads) {
   const long long V1 = g.voxels(), V2 = V1 / 8, V3 = V1 / 64, V4 = V1 / 512;
-  // activation channels per level
-  const long long act_elems = V1 * (8 + 16 + 16 + 48 + 16 + 16) + V2 * (16 + 32 + 32 + 96 + 32 + 32) +
-                              V3 * (32 + 64 + 64 + 192 + 64 + 64) + V4 * (64 + 128 + 128);
+  // activation channels per level; the concatenated decoder inputs only for
+  // training (inference reads them in place)
+  const long long cat_elems = grads ? V1 * 48 + V2 * 96 + V3 * 192 : 0;
+  const long long act_elems = V1 * (8 + 16 + 16 + 16 + 16) + V2 * (16 + 32 + 32 + 32 + 32) +
+                              V3 * (32 + 64 + 64 + 64 + 64) + V4 * (64 + 128 + 128) + cat_elems;
   const long long grad_elems = V1 * (16 + 16 + 48 + 16 + 16) + V2 * (32 + 32 + 96 + 32 + 32 + 16) +
                                V3 * (64 + 64 + 192 + 64 + 64 + 32) + V4 * (128 + 128 + 64);
   HIP_TRY(n->act.ensure((size_t)act_elems));
@@ -268,19 +270,19 @@ static fe_status ensure_workspace(fe_unet* n, const Grid3& g, bool grads) {
   n->x0 = take(V1 * 8);
   n->e1a = take(V1 * 16);
   n->e1 = take(V1 * 16);
-  n->cat1 = take(V1 * 48);
+  n->cat1 = grads ? take(V1 * 48) : nullptr;
   n->d1a = take(V1 * 16);
   n->d1 = take(V1 * 16);
   n->p1 = take(V2 * 16);
   n->e2a = take(V2 * 32);
   n->e2 = take(V2 * 32);
-  n->cat2 = take(V2 * 96);
+  n->cat2 = grads ? take(V2 * 96) : nullptr;
   n->d2a = take(V2 * 32);
   n->d2 = take(V2 * 32);
   n->p2 = take(V3 * 32);
   n->e3a = take(V3 * 64);
   n->e3 = take(V3 * 64);
-  n->cat3 = take(V3 * 192);
+  n->cat3 = grads ? take(V3 * 192) : nullptr;
   n->d3a = take(V3 * 64);
   n->d3 = take(V3 * 64);
   n->p3 = take(V4 * 64);
@@ -379,7 +381,15 @@ static void conv(fe_unet* n, int l, const uint16_t* x, uint16_t* y, const Grid3&
   conv3_forward(kDef[l].cin, kDef[l].cout, x, nullptr, n->wf[l], n->theta + n->off_b[l], 1, y, g, n->s);
 }
 
-static void forward(fe_unet* n, const uint8_t* phase, const Grid3& g1) {
+// decoder layer l on [up2(coarse), skip] read in place (no concatenated input)
+static void conv_cat(fe_unet* n, int l, int ca, const uint16_t* coarse, const uint16_t* skip, uint16_t* y,
+                     const Grid3& g) {
+  conv3_forward_cat(kDef[l].cin, kDef[l].cout, ca, coarse, skip, n->wf[l], n->theta + n->off_b[l], 1, y, g, n->s);
+}
+
+// With cat_in_place the decoder layers read their concatenated inputs in place
+// (inference); training keeps the concatenations, which the weight gradients read.
+static void forward(fe_unet* n, const uint8_t* phase, const Grid3& g1, bool cat_in_place) {
   const Grid3 g2 = coarse(g1), g3 = coarse(g2), g4 = coarse(g3);
   features(phase, n->tabs.p, n->x0, g1, n->s);
   conv(n, ENC1A, n->x0, n->e1a, g1);
@@ -393,14 +403,26 @@ static void forward(fe_unet* n, const uint8_t* phase, const Grid3& g1) {
   pool2(n->e3, 64, n->p3, g3, n->s);
   conv(n, BOTA, n->p3, n->ba, g4);
   conv(n, BOTB, n->ba, n->bt, g4);
-  up_concat(n->bt, 128, n->e3, 64, n->cat3, g3, n->s);
-  conv(n, DEC3A, n->cat3, n->d3a, g3);
+  if (cat_in_place) {
+    conv_cat(n, DEC3A, 128, n->bt, n->e3, n->d3a, g3);
+  } else {
+    up_concat(n->bt, 128, n->e3, 64, n->cat3, g3, n->s);
+    conv(n, DEC3A, n->cat3, n->d3a, g3);
+  }
   conv(n, DEC3B, n->d3a, n->d3, g3);
-  up_concat(n->d3, 64, n->e2, 32, n->cat2, g2, n->s);
-  conv(n, DEC2A, n->cat2, n->d2a, g2);
+  if (cat_in_place) {
+    conv_cat(n, DEC2A, 64, n->d3, n->e2, n->d2a, g2);
+  } else {
+    up_concat(n->d3, 64, n->e2, 32, n->cat2, g2, n->s);
+    conv(n, DEC2A, n->cat2, n->d2a, g2);
+  }
   conv(n, DEC2B, n->d2a, n->d2, g2);
-  up_concat(n->d2, 32, n->e1, 16, n->cat1, g1, n->s);
-  conv(n, DEC1A, n->cat1, n->d1a, g1);
+  if (cat_in_place) {
+    conv_cat(n, DEC1A, 32, n->d2, n->e1, n->d1a, g1);
+  } else {
+    up_concat(n->d2, 32, n->e1, 16, n->cat1, g1, n->s);
+    conv(n, DEC1A, n->cat1, n->d1a, g1);
+  }
   conv(n, DEC1B, n->d1a, n->d1, g1);
 }
 
@@ -451,7 +473,7 @@ extern "C" fe_status fe_unet_predict(fe_unet* n, const fe_unet_batch* b, void* o
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, n->s));
-  forward(n, b->phase, g);
+  forward(n, b->phase, g, true);
   head_stats(n->d1, n->theta + n->off_hw, n->theta + n->off_hb, nullptr, 0, n->hpart.p, n->sums.p, g, n->s);
   head_predict(n->d1, n->theta + n->off_hw, n->theta + n->off_hb, n->sums.p, n->tabs.p, static_cast<float*>(out), g,
                n->s);
@@ -475,7 +497,7 @@ static fe_status loss_grad(fe_unet* n, const fe_unet_batch* b, const void* targe
   if (st != FE_OK) return st;
   if ((st = ensure_workspace(n, g, true)) != FE_OK) return st;
   if ((st = upload_tabs(n, b)) != FE_OK) return st;
-  forward(n, b->phase, g);
+  forward(n, b->phase, g, false);
   const float* hw = n->theta + n->off_hw;
   const float* hb = n->theta + n->off_hb;
   head_stats(n->d1, hw, hb, target, tbf16, n->hpart.p, n->sums.p, g, n->s);
@@ -543,6 +565,28 @@ extern "C" fe_status fe_nn_conv3_forward(const fe_nn_conv_shape* sh, const uint1
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(wp);
   if (e != hipSuccess) return fail(FE_ERR_DEVICE, "conv3 forward: %s", hipGetErrorString(e));
+  return FE_OK;
+}
+
+extern "C" fe_status fe_nn_conv3_forward_cat(const fe_nn_conv_shape* sh, int32_t ca, const uint16_t* coarse,
+                                             const uint16_t* skip, const float* w, const float* b, int32_t relu,
+                                             uint16_t* y, void* stream) {
+  Grid3 g;
+  fe_status st = check_shape(sh, &g);
+  if (st != FE_OK) return st;
+  if (!conv_cat_supported(sh->c_in, sh->c_out, ca))
+    return fail(FE_ERR_UNSUPPORTED, "(c_in, c_out, c_coarse) = (%d, %d, %d)", sh->c_in, sh->c_out, ca);
+  if (g.nx % 2 || g.ny % 2 || g.nz % 2) return fail(FE_ERR_INVALID_ARG, "the grid must be even in each direction");
+  if (!coarse || !skip || !w || !y) return fail(FE_ERR_INVALID_ARG, "coarse, skip, w or y is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  uint16_t* wp = nullptr;
+  HIP_TRY(hipMalloc((void**)&wp, packed_elems(sh->c_in, sh->c_out) * sizeof(uint16_t)));
+  pack_weights(w, sh->c_in, sh->c_out, 0, wp, s);
+  conv3_forward_cat(sh->c_in, sh->c_out, ca, coarse, skip, wp, b, relu ? 1 : 0, y, g, s);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(wp);
+  if (e != hipSuccess) return fail(FE_ERR_DEVICE, "conv3 forward (concatenated input): %s", hipGetErrorString(e));
   return FE_OK;
 }
 

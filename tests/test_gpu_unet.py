@@ -86,6 +86,30 @@ def test_conv_forward(cin, cout, shape):
     assert np.mean(y == U.bf16(ref)) >= 0.999
 
 
+@pytest.mark.parametrize("cin,cout,ccoarse", [(48, 16, 32), (96, 32, 64), (192, 64, 128)])
+@pytest.mark.parametrize("relu", [True, False])
+def test_decoder_layer_reads_its_concatenation_in_place(cin, cout, ccoarse, relu):
+    """The decoder layers of inference read [nearest upsampling of the coarse
+    level, skip] in place; the result equals the layer on the materialised
+    concatenation bit for bit (same staged values, same products), and the
+    oracle on that concatenation within the layer bound."""
+    shape = (2, 6, 8, 20)  # (B, nz, ny, nx): even, tiles ragged in y and x
+    r = np.random.default_rng(cin + cout)
+    _, w, b = _conv_case(cin, cout, shape, 11 * cin + cout)
+    coarse = bf16_round(r.standard_normal((shape[0], shape[1] // 2, shape[2] // 2, shape[3] // 2, ccoarse)))
+    skip = bf16_round(r.standard_normal(shape + (cin - ccoarse,)))
+    up = coarse.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)
+    cat = np.concatenate([up, skip], axis=-1)
+    y = fe.conv3_forward_cat(dev_bf16(coarse), dev_bf16(skip), dev_f32(w), dev_f32(b), relu=relu)
+    y_cat = fe.conv3_forward(dev_bf16(cat), dev_f32(w), dev_f32(b), relu=relu)
+    assert torch.equal(y.view(torch.int16), y_cat.view(torch.int16))
+    ref = U.conv3(cat, w, b)
+    if relu:
+        ref = np.maximum(ref, 0.0)
+    absum = U.conv3(np.abs(cat), np.abs(w), np.zeros(cout))
+    assert np.all(np.abs(host_bf16(y) - ref) <= 2.0 ** -8 * np.abs(ref) + 2.0 ** -16 * absum)
+
+
 @pytest.mark.parametrize("cin,cout", [s for s in FWD if s[0] % 16 == 0])
 def test_conv_backward_data(cin, cout):
     shape = (2, 5, 6, 20)
