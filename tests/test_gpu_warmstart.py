@@ -5,7 +5,7 @@ definition), the solve from it reaches the same equilibrium, and it saves
 iterations, no more than the contraction model allows: a start whose error
 is e times that of eps_bar saves at most about log(e) / log(rho) iterations
 (rho: the plain run's contraction per iteration).  Measured on 16 cells at
-512^3: 0.94 iterations saved per cell against a prediction that costs 7.2."""
+512^3: 0.94 iterations saved per cell against a prediction that costs 5.8."""
 import os
 
 import numpy as np
