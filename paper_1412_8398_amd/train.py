@@ -83,8 +83,9 @@ class Dataset:
     def voxels(self):
         return sum(s.L ** 3 for s in self.samples)
 
-    def solve(self, tol=1e-6, max_iter=1500, chunk=512):
-        """Strain targets from batched solves of ``chunk`` samples at a time."""
+    def solve(self, tol=1e-6, max_iter=1500, chunk=512, launch="per_pass"):
+        """Strain targets from batched solves of ``chunk`` samples at a time
+        (``launch``: fe_plan_options.batch_launch, "per_pass" or "persistent")."""
         import torch
 
         import paper_1412_8398_amd as fe
@@ -102,7 +103,8 @@ class Dataset:
                 specs.append(fe.BatchSampleSpec(self.classes[L]["phase"][k], [1.0, s.contrast], [s.nu, s.nu],
                                                 s.macro_strain, eps))
                 outs.append((i, L, k, eps))
-            res, status, sec = fe.solve_batched(specs, tol, green="R", scheme="AS", precision="fp32", max_iter=max_iter)
+            res, status, sec = fe.solve_batched(specs, tol, green="R", scheme="AS", precision="fp32", max_iter=max_iter,
+                                                launch=launch)
             for (i, L, k, eps), r in zip(outs, res):
                 self.classes[L]["target"][k].copy_(eps.to(torch.bfloat16))
                 self.iterations[i], self.status[i], self.eta[i] = r.iterations, r.status, r.eta
@@ -198,6 +200,8 @@ def main(argv=None):
     ap.add_argument("--batch-voxels", type=int, default=1 << 20)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=1500)
+    ap.add_argument("--launch", choices=["per_pass", "persistent"], default="per_pass",
+                    help="batched-solve launch of the data generation (per_pass is the faster on MI355X)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--time-budget", type=float, default=None, help="seconds of training at most")
     ap.add_argument("--init", default=None, help="start from these parameters (.npy)")
@@ -217,9 +221,9 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "training needs a GPU"
     data = Dataset(train_s)
-    rep = {"data": data.solve(args.tol, args.max_iter)}
+    rep = {"data": data.solve(args.tol, args.max_iter, launch=args.launch)}
     val = Dataset(val_s)
-    rep["val_data"] = val.solve(args.tol, args.max_iter)
+    rep["val_data"] = val.solve(args.tol, args.max_iter, launch=args.launch)
     net = fe.UNet(lr=args.lr)
     if args.init:
         net.set_params(np.load(args.init))
