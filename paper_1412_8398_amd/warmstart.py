@@ -40,6 +40,23 @@ def load_net(path=DEFAULT_WEIGHTS):
     return net
 
 
+def solve_from_prediction(plan, net, phase, E, nu, macro, tol, strain, pred, history=1):
+    """The learned warm start with the applied strain as its fallback: the
+    network's prediction (written to ``pred``, device float32 (1, 6, nz, ny, nx))
+    starts the plan's solve; a start the scheme cannot bring to equilibrium
+    (FE_DIVERGED: eta not finite, or rising for the divergence window) is
+    dropped and the solve restarts from eps^0 = eps_bar.  Returns
+    (result, predict_seconds, fell_back)."""
+    import paper_1412_8398_amd as fe
+
+    _, t_pred = net.predict(phase.unsqueeze(0), [E], [nu], [macro], out=pred)
+    r = plan.solve(phase, E, nu, macro, tol, strain_init=pred[0], strain=strain, history=history,
+                   raise_on_error=False)
+    if r.status == fe.FE_DIVERGED:
+        return plan.solve(phase, E, nu, macro, tol, strain=strain, history=history, raise_on_error=False), t_pred, True
+    return r, t_pred, False
+
+
 def compare_one(net, phase, E, nu, macro, tol=1e-6, max_iter=3000, plan=None):
     """Plain and learned solves of one cell; returns a dict of measurements.
     ``phase`` is a device uint8 tensor (nz, ny, nx)."""
@@ -59,8 +76,7 @@ def compare_one(net, phase, E, nu, macro, tol=1e-6, max_iter=3000, plan=None):
     rp = plan.solve(phase, E, nu, macro, tol, strain=eps_p, history=1, raise_on_error=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    _, t_pred = net.predict(phase.unsqueeze(0), [E], [nu], [macro], out=pred)
-    rl = plan.solve(phase, E, nu, macro, tol, strain_init=pred[0], strain=eps_l, history=1, raise_on_error=False)
+    rl, t_pred, fell_back = solve_from_prediction(plan, net, phase, E, nu, macro, tol, eps_l, pred)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     mac = torch.tensor(np.asarray(macro, dtype=np.float32), device=phase.device).view(6, 1, 1, 1)
@@ -76,7 +92,8 @@ def compare_one(net, phase, E, nu, macro, tol=1e-6, max_iter=3000, plan=None):
         "plain": {"iterations": rp.iterations, "seconds": t1 - t0, "eta0": float(rp.eta_history[0]),
                   "eta": rp.eta_verify_fp64, "status": rp.status},
         "learned": {"iterations": rl.iterations, "seconds": t2 - t1, "predict_seconds": t_pred,
-                    "eta0": float(rl.eta_history[0]), "eta": rl.eta_verify_fp64, "status": rl.status},
+                    "eta0": float(rl.eta_history[0]), "eta": rl.eta_verify_fp64, "status": rl.status,
+                    "fell_back": fell_back},
         "prediction_rel_l2": pred_err,
         "mean_stress_rel_diff": float(np.linalg.norm(sl - sp) / max(np.linalg.norm(sp), 1e-300)),
         "rho": rho,

@@ -44,3 +44,27 @@ def test_learned_start_is_closer_and_converges_to_the_same_answer():
     saved = sum(r["iterations_saved"] for r in rows)
     bound = sum(max(r["iterations_saved_model"], 0.0) + 1.0 for r in rows)
     assert saved <= bound, (saved, bound)
+
+
+def test_a_start_that_cannot_converge_falls_back_to_the_applied_strain():
+    """A prediction the scheme cannot bring to equilibrium (here: not finite)
+    ends FE_DIVERGED; the warm-start solve then restarts from eps_bar and
+    returns the plain solution."""
+    from paper_1412_8398_amd.warmstart import solve_from_prediction
+
+    class _NaNNet:  # stands in for the network: predicts a non-finite strain
+        def predict(self, phase, E, nu, macro, out):
+            out.fill_(float("nan"))
+            return out, 0.0
+
+    s = batch_samples(1, 778, sizes=(32,))[0]
+    ph = torch.from_numpy(s.phase).cuda()
+    E, nu = [1.0, s.contrast], [s.nu, s.nu]
+    with fe.Plan(32, green="R", scheme="AS", precision="fp32", max_iter=3000) as plan:
+        plain = plan.solve(ph, E, nu, s.macro_strain, 1e-6, history=1, raise_on_error=False)
+        pred = torch.empty((1, 6, 32, 32, 32), dtype=torch.float32, device="cuda")
+        eps = torch.empty((6, 32, 32, 32), dtype=torch.float32, device="cuda")
+        r, _, fell_back = solve_from_prediction(plan, _NaNNet(), ph, E, nu, s.macro_strain, 1e-6, eps, pred)
+    assert fell_back
+    assert r.status == fe.FE_OK == plain.status and r.iterations == plain.iterations
+    assert np.array_equal(np.asarray(r.mean_stress), np.asarray(plain.mean_stress))
