@@ -1709,22 +1709,53 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
     results[i].status = FE_NOT_CONVERGED;
     results[i].iterations = 0;
   }
+  // one stream per grid class (default priority): the classes are
+  // independent, so their launches overlap and small grids fill the chip
+  // together; every iteration joins them on the host
+  struct Streams {
+    std::vector<hipStream_t> v;
+    std::vector<hipEvent_t> ev;
+    ~Streams() {
+      for (hipStream_t q : v) (void)hipStreamDestroy(q);
+      for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+  } cs;
+  for (size_t c = 0; c < cls.size(); ++c) {
+    hipStream_t q = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    cs.v.push_back(q);
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    cs.ev.push_back(e);
+  }
+  auto join = [&]() -> fe_status {
+    for (hipStream_t q : cs.v) HIP_TRY(hipStreamSynchronize(q));
+    return FE_OK;
+  };
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, s));
+  for (hipStream_t q : cs.v) HIP_TRY(hipStreamWaitEvent(q, e0, 0));
   std::vector<double> hred;
   // eta^0: divergence of eps_bar for every sample
-  for (auto& c : cls) {
+  for (size_t ci = 0; ci < cls.size(); ++ci) {
+    auto& c = cls[ci];
+    hipStream_t s = cs.v[ci];
     const int na = (int)c.act.size();
     const Batch bt{c.active, c.ncoef};
     const int nb = Launch<T>::div(c.cur, c.phase, c.coef, c.R, nullptr, c.partials, c.d, op, s, bt, na);
     launch_reduce(c.partials, nb, 7, c.red, s, c.active, na);
   }
   for (int k = 0;; ++k) {
-    HIP_TRY(hipStreamSynchronize(s));
+    {
+      fe_status js = join();
+      if (js != FE_OK) return js;
+    }
     bool left = false;
-    for (auto& c : cls) {
+    for (size_t ci = 0; ci < cls.size(); ++ci) {
+      auto& c = cls[ci];
+      hipStream_t s = cs.v[ci];
       if (c.act.empty()) continue;
       hred.resize(c.ids.size() * 8);
       HIP_TRY(hipMemcpy(hred.data(), c.red, hred.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -1775,7 +1806,9 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
       }
     }
     if (!left) break;
-    for (auto& c : cls) {
+    for (size_t ci = 0; ci < cls.size(); ++ci) {
+      auto& c = cls[ci];
+      hipStream_t s = cs.v[ci];
       const int na = (int)c.act.size();
       if (!na) continue;
       const Batch bt{c.active, c.ncoef};
@@ -1794,6 +1827,10 @@ fe_status solve_batched_impl(int op, bool accel, const fe_plan_options& o, const
       std::swap(c.R, c.R2);
     }
     HIP_TRY(hipGetLastError());
+  }
+  for (size_t ci = 0; ci < cls.size(); ++ci) {  // the caller's stream after every class
+    HIP_TRY(hipEventRecord(cs.ev[ci], cs.v[ci]));
+    HIP_TRY(hipStreamWaitEvent(s, cs.ev[ci], 0));
   }
   HIP_TRY(hipEventRecord(e1, s));
   HIP_TRY(hipEventSynchronize(e1));
