@@ -252,8 +252,10 @@ fe_status fe_effective_stiffness(fe_plan* plan, const uint8_t* phase, fe_materia
  *   (the default) a sample whose float32 strain does not verify to tol
  *   continues with float64 fields from it (one launch per pass per iteration
  *   over those samples only); its strain is returned rounded to float32,
- *   verified again, and FE_OK only if that verification meets tol;
- *   iterations counts both phases.
+ *   verified again, and FE_OK only if that verification meets tol (a sample
+ *   that reached tol in float64 but misses it after the rounding continues
+ *   again with tol halved, at most four times, while its verified eta keeps
+ *   falling); iterations counts every phase.
  *   Float64: one launch per pass per iteration (FE_BATCH_PERSISTENT gives
  *   FE_ERR_UNSUPPORTED).
  *   desc->phase[i]   device, N_i uint8 labels of sample i

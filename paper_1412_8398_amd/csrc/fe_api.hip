@@ -2151,7 +2151,12 @@ fe_status solve_batched_f32(int op, bool accel, const fe_plan_options& o, const 
         redo.emplace_back((int)c, (int)j);
     }
   }
-  if (!redo.empty()) {
+  // A continuation that reached its target in float64 can still miss tol once
+  // its strain is rounded to float32; such samples continue again from the
+  // rounded strain with the target halved (at most four times, and only while
+  // the verified eta keeps falling).
+  double target = tol;
+  for (int lowered = 0; !redo.empty(); ++lowered) {
     const int nr = (int)redo.size();
     std::vector<fe_grid> grids(nr);
     std::vector<const uint8_t*> phases(nr);
@@ -2182,7 +2187,7 @@ fe_status solve_batched_f32(int op, bool accel, const fe_plan_options& o, const 
     fe_plan_options o64 = o;
     o64.precision = FE_FP64;
     double sec64 = 0.0;
-    const fe_status st64 = solve_batched_impl<double>(op, accel, o64, &sd, tol, sub.data(), &sec64, init.data());
+    const fe_status st64 = solve_batched_impl<double>(op, accel, o64, &sd, target, sub.data(), &sec64, init.data());
     if (st64 < 0) return st64;
     if (seconds) *seconds += sec64;
     for (int k = 0; k < nr; ++k) {
@@ -2195,12 +2200,23 @@ fe_status solve_batched_f32(int op, bool accel, const fe_plan_options& o, const 
       for (int q = 0; q < 6; ++q) r.mean_stress[q] = sub[k].mean_stress[q];
       r.status = sub[k].status;
     }
+    std::vector<double> last(nr);
+    for (int k = 0; k < nr; ++k) last[k] = results[cls[redo[k].first].ids[redo[k].second]].eta_verify_fp64;
     for (F32Class& c : cls) {  // the returned float32 strains, verified again
       std::vector<double> ev;
       fe_status vs = verify(c, ev);
       if (vs != FE_OK) return vs;
       for (size_t j = 0; j < c.ids.size(); ++j) results[c.ids[j]].eta_verify_fp64 = ev[j];
     }
+    std::vector<std::pair<int, int>> again;
+    for (int k = 0; k < nr; ++k) {
+      const fe_batch_result& r = results[cls[redo[k].first].ids[redo[k].second]];
+      if (r.status == FE_OK && !(r.eta_verify_fp64 <= tol) && r.eta_verify_fp64 < 0.9 * last[k] &&
+          r.iterations < o.max_iter && lowered < 4)
+        again.push_back(redo[k]);
+    }
+    redo.swap(again);
+    target *= 0.5;
   }
   // with refinement FE_OK means the returned float32 strain verifies to tol
   // (a sample that cannot continue, or ends at the float32 storage floor of
