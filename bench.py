@@ -141,6 +141,46 @@ def time_to_tolerance(fe, torch, np, phase, E, nu, L, weights):
     return out
 
 
+def spectrum_bytes(L):
+    """Bytes of the three float32 half spectra of an L^3 cell as the solver
+    stores them (H = L/2 + 1 planes rounded up to the z blocking of 8)."""
+    zs = 3
+    while zs > 0 and L % (1 << zs):
+        zs -= 1
+    hp = ((L // 2 + 1 + (1 << zs) - 1) >> zs) << zs
+    return 3 * hp * L * L * 8
+
+
+def device_inplace(fe, torch, nbytes, reps=5):
+    """Bandwidth of the library's streaming kernel rewriting one buffer in
+    place (fe_stream_copy with dst == src), the access pattern of the in-place
+    transform passes, over ``nbytes`` (the workload's half spectra): read +
+    write counted, best of ``reps`` per variant."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    out = {"bytes": nbytes}
+
+    def best_of(nt):
+        fe.stream_copy(a, a, nt, st.cuda_stream)
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fe.stream_copy(a, a, nt, st.cuda_stream)
+            e1.record(st)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e-3)
+        return 2 * nbytes / best / 1e9
+
+    out["plain_gbs"] = round(best_of(False), 1)
+    out["nontemporal_gbs"] = round(best_of(True), 1)
+    out["gbs"] = max(out["plain_gbs"], out["nontemporal_gbs"])
+    out["kernel"] = "fe_stream_copy in place (dst == src) over the half spectra, best variant, best of 5"
+    del a
+    torch.cuda.empty_cache()
+    return out
+
+
 def device_copy(fe, torch, nbytes=1 << 31, reps=5):
     """Bandwidth of the library's streaming copy kernel (fe_stream_copy) on
     2 GiB, read + write counted, best of ``reps`` per variant (plain and
@@ -314,6 +354,9 @@ def main():
 
     # context for the roofline: the bandwidth a plain copy attains on this GPU
     copy = device_copy(fe, torch)
+    # and an in-place rewrite of a buffer the size of the half spectra (the
+    # transform passes read and write their buffer in place)
+    inplace = device_inplace(fe, torch, spectrum_bytes(L))
 
     # the paper's precision: the same K iterations with float64 fields
     fp64 = None
@@ -366,6 +409,7 @@ def main():
         "iteration_hbm_frac_model": round(iter_gbs / PEAK_HBM_GBS, 4),
         "device_copy": dict(copy, dominant_kernel_frac=round(passes[dom]["gbs"] / copy["gbs"], 4),
                             iteration_frac=round(iter_gbs / copy["gbs"], 4)),
+        "device_inplace": dict(inplace, iteration_frac=round(iter_gbs / inplace["gbs"], 4)),
         "fp64": fp64,
         "passes": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                    for k, v in passes.items()},

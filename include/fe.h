@@ -317,12 +317,14 @@ fe_status fe_solve_static(fe_grid grid, fe_discretization disc, fe_scheme scheme
 
 /*
  * Measurement reference: copy `bytes` (a multiple of 16) from src to dst,
- * both device memory, 16-byte aligned and not overlapping, with the
- * library's streaming copy kernel (16-byte vectors, all loads of a thread in
- * flight before its stores; nontemporal != 0 marks loads and stores as
- * streaming).  Asynchronous on hip_stream (NULL: the null stream).  The
- * solver's passes are compared with the bandwidth this kernel reaches.
- * Errors: FE_ERR_INVALID_ARG (NULL, size or alignment, overlap).
+ * both device memory, 16-byte aligned, with the library's streaming copy
+ * kernel (16-byte vectors, all loads of a thread in flight before its
+ * stores; nontemporal != 0 marks loads and stores as streaming).  dst == src
+ * rewrites the buffer in place (each vector read and written back: the
+ * access pattern of the solver's in-place passes); other overlaps are
+ * errors.  Asynchronous on hip_stream (NULL: the null stream).  The solver's
+ * passes are compared with the bandwidth this kernel reaches.
+ * Errors: FE_ERR_INVALID_ARG (NULL, size or alignment, partial overlap).
  */
 fe_status fe_stream_copy(void* dst, const void* src, size_t bytes, int32_t nontemporal, void* hip_stream);
 

@@ -351,7 +351,8 @@ class Plan:
 
 def stream_copy(dst, src, nontemporal=False, stream=None):
     """fe_stream_copy between two device tensors of the same byte size (the
-    measurement reference for attainable HBM bandwidth)."""
+    measurement reference for attainable HBM bandwidth); ``dst is src``
+    rewrites the tensor in place."""
     import torch
     for name, t in (("dst", dst), ("src", src)):
         if not isinstance(t, torch.Tensor) or not t.is_contiguous():

@@ -41,6 +41,29 @@ __global__ __launch_bounds__(kCopyThreads) void k_copy16(const v4u* __restrict__
   }
 }
 
+// In place (dst == src): every thread rewrites the vectors it has just read,
+// so the pointers may alias (no __restrict__).
+template <bool NT>
+__global__ __launch_bounds__(kCopyThreads) void k_rewrite16(v4u* p, long long n) {
+  const long long base = (long long)blockIdx.x * kCopyThreads * kCopyUnroll + threadIdx.x;
+  v4u v[kCopyUnroll];
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const long long j = base + (long long)u * kCopyThreads;
+    if (j < n) v[u] = NT ? __builtin_nontemporal_load(p + j) : p[j];
+  }
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const long long j = base + (long long)u * kCopyThreads;
+    if (j < n) {
+      if (NT)
+        __builtin_nontemporal_store(v[u], p + j);
+      else
+        p[j] = v[u];
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" fe_status fe_stream_copy(void* dst, const void* src, size_t bytes, int32_t nontemporal, void* hip_stream) {
@@ -50,14 +73,19 @@ extern "C" fe_status fe_stream_copy(void* dst, const void* src, size_t bytes, in
     return fail(FE_ERR_INVALID_ARG, "dst and src must be 16-byte aligned");
   const char* s = static_cast<const char*>(src);
   const char* d = static_cast<const char*>(dst);
-  if (s < d + bytes && d < s + bytes) return fail(FE_ERR_INVALID_ARG, "dst and src overlap");
+  if (s != d && s < d + bytes && d < s + bytes) return fail(FE_ERR_INVALID_ARG, "dst and src overlap");
   const long long n = (long long)(bytes / 16);
   if (n == 0) return FE_OK;
   const long long per_block = (long long)kCopyThreads * kCopyUnroll;
   const long long blocks = (n + per_block - 1) / per_block;
   if (blocks > 0x7fffffffLL) return fail(FE_ERR_UNSUPPORTED, "copy too large");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  if (nontemporal)
+  if (s == d) {
+    if (nontemporal)
+      hipLaunchKernelGGL(k_rewrite16<true>, dim3((unsigned)blocks), dim3(kCopyThreads), 0, st, static_cast<v4u*>(dst), n);
+    else
+      hipLaunchKernelGGL(k_rewrite16<false>, dim3((unsigned)blocks), dim3(kCopyThreads), 0, st, static_cast<v4u*>(dst), n);
+  } else if (nontemporal)
     hipLaunchKernelGGL(k_copy16<true>, dim3((unsigned)blocks), dim3(kCopyThreads), 0, st,
                        static_cast<const v4u*>(src), static_cast<v4u*>(dst), n);
   else

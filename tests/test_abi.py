@@ -171,3 +171,17 @@ def test_ctypes_structures_match_the_c_headers(tmp_path):
     subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     assert got == want
+
+
+def test_stream_copy_rejects_bad_arguments_before_device_work(lib):
+    """Checked on the host before any launch: NULL, sizes that are not whole
+    16-byte vectors, misalignment and partial overlap (dst == src is the
+    in-place rewrite and allowed; these addresses are never dereferenced)."""
+    call = lambda d, s, n: lib.fe_stream_copy(d, s, n, 0, None)  # noqa: E731
+    assert call(None, 0x1000, 64) == fe.FE_ERR_INVALID_ARG
+    assert call(0x1000, None, 64) == fe.FE_ERR_INVALID_ARG
+    assert call(0x2000, 0x1000, 40) == fe.FE_ERR_INVALID_ARG
+    assert call(0x2008, 0x1000, 64) == fe.FE_ERR_INVALID_ARG
+    assert call(0x1010, 0x1000, 64) == fe.FE_ERR_INVALID_ARG
+    assert call(0x1000, 0x1030, 64) == fe.FE_ERR_INVALID_ARG
+    assert call(0x2000, 0x1000, 0) == fe.FE_OK
