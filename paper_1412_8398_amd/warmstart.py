@@ -5,7 +5,7 @@ operator (float32 fields, float64 reductions and re-anchoring) to the same
 equilibrium tolerance; the learned run starts from the network's prediction
 and its time includes the prediction.
 
-    python -m paper_1412_8398_amd.warmstart --weights w.npy --size 128 --count 16
+    python -m paper_1412_8398_amd.warmstart --weights w.npy --size 128 --count 16 [--scaled]
 
 Break-even model, per cell.  The scheme contracts the error of its iterate by
 a factor rho per iteration (measured: rho = (eta_end / eta_0)^(1/k) of the
@@ -57,7 +57,30 @@ def solve_from_prediction(plan, net, phase, E, nu, macro, tol, strain, pred, his
     return r, t_pred, False
 
 
-def compare_one(net, phase, E, nu, macro, tol=1e-6, max_iter=3000, plan=None):
+def scaled_starts(plan, phase, E, nu, macro, tol, eps_star, pred, scales=(0.5, 0.25, 0.1), shares=(0.5, 0.3, 0.1)):
+    """Iterations from starts a better prediction could give, around the
+    converged strain eps_star (6, nz, ny, nx):
+      "pred_x<s>":  eps_star + s (pred - eps_star), the network's own error
+                    scaled by s (same shape, e times s);
+      "fluct_e<e>": eps_bar + (1 - e)(eps_star - eps_bar), the exact
+                    fluctuation scaled down (relative error e, the shape of
+                    the solution itself).
+    Returns {label: iterations}."""
+    import torch
+
+    mac = torch.tensor(np.asarray(macro, dtype=np.float32), device=phase.device).view(6, 1, 1, 1)
+    out = {}
+    start = torch.empty_like(eps_star)
+    eps = torch.empty_like(eps_star)
+    for label, make in ([(f"pred_x{sc:g}", lambda sc=sc: eps_star + sc * (pred - eps_star)) for sc in scales] +
+                        [(f"fluct_e{e:g}", lambda e=e: mac + (1.0 - e) * (eps_star - mac)) for e in shares]):
+        start.copy_(make())
+        r = plan.solve(phase, E, nu, macro, tol, strain_init=start, strain=eps, history=1, raise_on_error=False)
+        out[label] = int(r.iterations) if r.status == 0 else None
+    return out
+
+
+def compare_one(net, phase, E, nu, macro, tol=1e-6, max_iter=3000, plan=None, scaled=False):
     """Plain and learned solves of one cell; returns a dict of measurements.
     ``phase`` is a device uint8 tensor (nz, ny, nx)."""
     import torch
@@ -103,6 +126,8 @@ def compare_one(net, phase, E, nu, macro, tol=1e-6, max_iter=3000, plan=None):
         "iterations_saved_model": float(np.log(pred_err) / np.log(rho)) if 0 < rho < 1 else float("nan"),
         "e_breakeven": float(rho ** cost) if 0 < rho < 1 else float("nan"),
     }
+    if scaled:
+        out["scaled_starts"] = scaled_starts(plan, phase, E, nu, macro, tol, eps_p, pred[0])
     if own:
         plan.close()
     return out
@@ -116,6 +141,8 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=5141230)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--scaled", action="store_true",
+                    help="also solve from the network's error scaled down and from scaled exact fluctuations")
     args = ap.parse_args(argv)
 
     from microstructure import batch_samples
@@ -133,7 +160,8 @@ def main(argv=None):
                     args.tol, plan=plan)
         for i, s in enumerate(samples):
             ph = torch.from_numpy(s.phase).cuda()
-            r = compare_one(net, ph, [1.0, s.contrast], [s.nu, s.nu], s.macro_strain, args.tol, plan=plan)
+            r = compare_one(net, ph, [1.0, s.contrast], [s.nu, s.nu], s.macro_strain, args.tol, plan=plan,
+                            scaled=args.scaled)
             r.update({"sample": i, "L": s.L, "contrast": s.contrast, "fraction": s.volume_fraction, "radius": s.radius,
                       "nu": s.nu, "load": s.load, "seed": s.seed})
             rows.append(r)
@@ -155,6 +183,19 @@ def main(argv=None):
             "iterations_saved_mean": float(np.mean([r["iterations_saved"] for r in rows])),
             "iterations_saved_model_mean": float(np.mean([r["iterations_saved_model"] for r in rows])),
             "e_breakeven_median": float(np.median([r["e_breakeven"] for r in rows]))}
+    if args.scaled:
+        # iterations saved against the plain start, per start family, over all
+        # cells and over the slow ones (rho > 0.8), beside the prediction's cost
+        labels = list(rows[0]["scaled_starts"])
+        slow = [r for r in rows if r["rho"] > 0.8]
+        saved = {}
+        for lab in labels:
+            d_all = [r["plain"]["iterations"] - r["scaled_starts"][lab] for r in rows if r["scaled_starts"][lab] is not None]
+            d_slow = [r["plain"]["iterations"] - r["scaled_starts"][lab] for r in slow
+                      if r["scaled_starts"][lab] is not None]
+            saved[lab] = {"mean": float(np.mean(d_all)) if d_all else None,
+                          "mean_rho_gt_0.8": float(np.mean(d_slow)) if d_slow else None}
+        summ["scaled_starts_saved"] = saved
     print(json.dumps({"summary": summ}), flush=True)
     if args.out:
         with open(args.out, "w") as fh:
