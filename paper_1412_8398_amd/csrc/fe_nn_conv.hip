@@ -86,23 +86,66 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
   const int slot = (grp * 8) / CCH, pc = ((grp * 8) % CCH) / 8;
 
   static_assert(CA % CCH == 0 && CA < CIN, "channel chunks within one source");
+  static_assert(!(MASKED && CA > 0), "masked inputs come from one source");
   for (int ch = 0; ch < NCH; ++ch) {
     if (ch) __syncthreads();
     const bool from_coarse = CA > 0 && ch * CCH < CA;
-    for (int i = threadIdx.x; i < HV * PIECES; i += 256) {
-      const int p = i % PIECES, hv = i / PIECES;
+    // Layers with at most 32 output channels have their halo loads in flight
+    // together before the first LDS store (a load-store pair per step waits
+    // out the memory latency once per step); the spare lanes of the last step
+    // re-read the last halo vector, so that no load sits under a branch, and
+    // the source test, uniform over the chunk, leaves each loop only its own
+    // addresses.  Wider layers, and the in-place decoder layer with 32-channel
+    // chunks, keep one load and store per step: the registers of the batched
+    // loads cost them occupancy (measured).
+    constexpr int NS = (HV * PIECES + 255) / 256;
+    constexpr bool BATCHED = MT <= 2 && !(CA > 0 && CCH == 32);
+    auto halo = [&](int i, int& p, int& gx, int& gy, int& gz) {
+      p = i % PIECES;
+      const int hv = i / PIECES;
       const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
-      const int gx = wrapi(tc.x0 - 1 + hx, g.nx), gy = wrapi(tc.y0 - 1 + hy, g.ny), gz = wrapi(tc.z0 - 1 + hz, g.nz);
-      u32x4 v;
+      gx = wrapi(tc.x0 - 1 + hx, g.nx);
+      gy = wrapi(tc.y0 - 1 + hy, g.ny);
+      gz = wrapi(tc.z0 - 1 + hz, g.nz);
+    };
+    auto coarse_at = [&](int p, int gx, int gy, int gz) {
+      const long long cv = (((long long)tc.smp * (g.nz / 2) + gz / 2) * (g.ny / 2) + gy / 2) * (g.nx / 2) + gx / 2;
+      return *reinterpret_cast<const u32x4*>(XC + cv * CA + ch * CCH + p * 8);
+    };
+    auto fine_at = [&](int p, int gx, int gy, int gz) {
+      const long long off = (((zb + gz) * g.ny + gy) * g.nx + gx) * (CIN - CA) + (ch * CCH - CA) + p * 8;
+      u32x4 v = *reinterpret_cast<const u32x4*>(X + off);
+      if (MASKED) v = mask8(v, *reinterpret_cast<const u32x4*>(M + off));
+      return v;
+    };
+    if (BATCHED) {
+      u32x4 st[NS];
       if (from_coarse) {
-        const long long cv = (((long long)tc.smp * (g.nz / 2) + gz / 2) * (g.ny / 2) + gy / 2) * (g.nx / 2) + gx / 2;
-        v = *reinterpret_cast<const u32x4*>(XC + cv * CA + ch * CCH + p * 8);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          int p, gx, gy, gz;
+          halo(min(threadIdx.x + q * 256, HV * PIECES - 1), p, gx, gy, gz);
+          st[q] = coarse_at(p, gx, gy, gz);
+        }
       } else {
-        const long long off = (((zb + gz) * g.ny + gy) * g.nx + gx) * (CIN - CA) + (ch * CCH - CA) + p * 8;
-        v = *reinterpret_cast<const u32x4*>(X + off);
-        if (MASKED) v = mask8(v, *reinterpret_cast<const u32x4*>(M + off));
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          int p, gx, gy, gz;
+          halo(min(threadIdx.x + q * 256, HV * PIECES - 1), p, gx, gy, gz);
+          st[q] = fine_at(p, gx, gy, gz);
+        }
       }
-      lds[i] = v;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int i = threadIdx.x + q * 256;
+        if (i < HV * PIECES) lds[i] = st[q];
+      }
+    } else {
+      for (int i = threadIdx.x; i < HV * PIECES; i += 256) {
+        int p, gx, gy, gz;
+        halo(i, p, gx, gy, gz);
+        lds[i] = from_coarse ? coarse_at(p, gx, gy, gz) : fine_at(p, gx, gy, gz);
+      }
     }
     __syncthreads();
     for (int gi = 0; gi < NG; ++gi) {
