@@ -87,6 +87,10 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
 
   static_assert(CA % CCH == 0 && CA < CIN, "channel chunks within one source");
   static_assert(!(MASKED && CA > 0), "masked inputs come from one source");
+  static_assert(TX % 2 == 0 && TY % 2 == 0 && TZ % 2 == 0, "tile origins even (coarse halo offsets)");
+  // the tile's halo lies inside the grid (no periodic wrap): uniform
+  const bool interior = tc.x0 >= 1 && tc.x0 - 1 + HX <= g.nx && tc.y0 >= 1 && tc.y0 - 1 + HY <= g.ny &&
+                        tc.z0 >= 1 && tc.z0 - 1 + HZ <= g.nz;
   for (int ch = 0; ch < NCH; ++ch) {
     if (ch) __syncthreads();
     const bool from_coarse = CA > 0 && ch * CCH < CA;
@@ -118,7 +122,41 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
       if (MASKED) v = mask8(v, *reinterpret_cast<const u32x4*>(M + off));
       return v;
     };
-    if (BATCHED) {
+    if (BATCHED && interior) {
+      // halo inside the grid: no periodic wrap, each address a uniform base
+      // plus a 32-bit offset (the general path's integer divisions and 64-bit
+      // products made the staging outweigh the products in issue slots)
+      u32x4 st[NS];
+      if (from_coarse) {
+        const int cnx = g.nx / 2, cny = g.ny / 2;
+        const long long cb = (((long long)tc.smp * (g.nz / 2) + tc.z0 / 2) * cny + tc.y0 / 2) * cnx + tc.x0 / 2;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          const int i = min(threadIdx.x + q * 256, HV * PIECES - 1);
+          const int p = i % PIECES, hv = i / PIECES;
+          const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+          // gz = z0 - 1 + hz with z0 even: gz / 2 = z0 / 2 + floor((hz - 1) / 2)
+          const int lc = (((hz - 1) >> 1) * cny + ((hy - 1) >> 1)) * cnx + ((hx - 1) >> 1);
+          st[q] = *reinterpret_cast<const u32x4*>(XC + (cb + lc) * CA + ch * CCH + p * 8);
+        }
+      } else {
+        const long long fb = ((zb + tc.z0 - 1) * g.ny + (tc.y0 - 1)) * (long long)g.nx + (tc.x0 - 1);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          const int i = min(threadIdx.x + q * 256, HV * PIECES - 1);
+          const int p = i % PIECES, hv = i / PIECES;
+          const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+          const long long off = (fb + (hz * g.ny + hy) * g.nx + hx) * (CIN - CA) + (ch * CCH - CA) + p * 8;
+          st[q] = *reinterpret_cast<const u32x4*>(X + off);
+          if (MASKED) st[q] = mask8(st[q], *reinterpret_cast<const u32x4*>(M + off));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int i = threadIdx.x + q * 256;
+        if (i < HV * PIECES) lds[i] = st[q];
+      }
+    } else if (BATCHED) {
       u32x4 st[NS];
       if (from_coarse) {
 #pragma unroll
