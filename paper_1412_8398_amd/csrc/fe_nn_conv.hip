@@ -309,20 +309,30 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ X, c
   for (int tap = 0; tap < 27; ++tap) out[tap * 64 + lane] = acc[tap];
 }
 
-// dw[t][c][o] = fixed-order sum over the partial sets
+// dw[t][c][o] = fixed-order sum over the partial sets: one workgroup per
+// (channel pair, tap), its 16 wavefronts each adding every 16th set for the
+// 64 lanes, then the 16 slice sums in order (one thread per lane walking all
+// sets waited out a load latency per set)
+constexpr int kWgradSlices = 16;
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_wgrad_reduce(const f32x4* __restrict__ partials, int nsets,
-                                                      float* __restrict__ dw) {
+__global__ __launch_bounds__(64 * kWgradSlices) void k_wgrad_reduce(const f32x4* __restrict__ partials, int nsets,
+                                                                     float* __restrict__ dw) {
   constexpr int CB = CIN < 16 ? CIN : 16;
-  constexpr int NOB = COUT / 16, NPAIR = (CIN / CB) * NOB;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // (pair, tap, lane)
-  if (idx >= NPAIR * 27 * 64) return;
-  const int lane = idx % 64, tap = (idx / 64) % 27, pair = idx / (64 * 27);
+  constexpr int NOB = COUT / 16;
+  __shared__ f32x4 red[kWgradSlices][64];
+  const int tap = blockIdx.x % 27, pair = blockIdx.x / 27;
+  const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  f32x4 s = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k = sl; k < nsets; k += kWgradSlices) s += partials[((long long)(pair * nsets + k) * 27 + tap) * 64 + lane];
+  red[sl][lane] = s;
+  __syncthreads();
+  if (sl != 0) return;
+  s = red[0][lane];
+#pragma unroll
+  for (int q = 1; q < kWgradSlices; ++q) s += red[q][lane];
   const int cib = pair / NOB, cob = pair % NOB;
   const int j = lane & 15, grp = lane >> 4;
   if (j >= CB) return;
-  f32x4 s = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k = 0; k < nsets; ++k) s += partials[((long long)(pair * nsets + k) * 27 + tap) * 64 + lane];
   const int ci = cib * CB + j;
 #pragma unroll
   for (int r = 0; r < 4; ++r) dw[((long long)tap * CIN + ci) * COUT + cob * 16 + 4 * grp + r] = s[r];
@@ -426,8 +436,8 @@ void conv3_wgrad_reduce(int cin, int cout, const float* partials, int nsets, flo
   const f32x4* p = reinterpret_cast<const f32x4*>(partials);
 #define FE_CASE(a, b)                                                                                 \
   if (cin == a && cout == b) {                                                                        \
-    const int pairs = (a < 16 ? 1 : a / 16) * (b / 16), n = pairs * 27 * 64;                          \
-    hipLaunchKernelGGL((k_wgrad_reduce<a, b>), dim3((n + 255) / 256), dim3(256), 0, s, p, nsets, dw); \
+    const int pairs = (a < 16 ? 1 : a / 16) * (b / 16);                                               \
+    hipLaunchKernelGGL((k_wgrad_reduce<a, b>), dim3(pairs * 27), dim3(64 * kWgradSlices), 0, s, p, nsets, dw); \
     return;                                                                                           \
   }
   FE_NN_CONV_SHAPES(FE_CASE)

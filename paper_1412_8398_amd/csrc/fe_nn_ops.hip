@@ -269,12 +269,16 @@ __global__ __launch_bounds__(256) void k_bias_partials(const uint16_t* __restric
   }
 }
 
-__global__ void k_bias_reduce(const float* __restrict__ partials, int nb, int c, float* __restrict__ db) {
-  const int ch = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ch >= c) return;
-  float s = 0.f;
-  for (int b = 0; b < nb; ++b) s += partials[b * c + ch];
-  db[ch] = s;
+// one workgroup of 256 per channel: thread t adds rows t, t + 256, ..., then
+// the fixed-order tree in float64
+__global__ __launch_bounds__(256) void k_bias_reduce(const float* __restrict__ partials, int nb, int c,
+                                                     float* __restrict__ db) {
+  __shared__ double red[4];
+  const int ch = blockIdx.x;
+  double acc[1] = {0.0};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc[0] += (double)partials[b * c + ch];
+  block_sum_d<1>(acc, red);
+  if (threadIdx.x == 0) db[ch] = (float)acc[0];
 }
 
 int bias_grad(const uint16_t* dy, const uint16_t* ymask, int c, float* partials, float* db, Grid3 g, hipStream_t s) {
@@ -282,7 +286,7 @@ int bias_grad(const uint16_t* dy, const uint16_t* ymask, int c, float* partials,
   long long nb = (V + (256 / c) - 1) / (256 / c);
   if (nb > kBiasBlocks) nb = kBiasBlocks;
   hipLaunchKernelGGL(k_bias_partials, dim3((int)nb), dim3(256), 0, s, dy, ymask, c, V, partials);
-  hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(256), 0, s, partials, (int)nb, c, db);
+  hipLaunchKernelGGL(k_bias_reduce, dim3(c), dim3(256), 0, s, partials, (int)nb, c, db);
   return (int)nb;
 }
 
@@ -345,12 +349,20 @@ __global__ __launch_bounds__(256) void k_head_stats(const u32x4* __restrict__ d1
     for (int i = 0; i < 12; ++i) partials[((long long)smp * gridDim.x + blockIdx.x) * 12 + i] = acc[i];
 }
 
-__global__ void k_head_sums(const double* __restrict__ partials, int nblk, double* __restrict__ sums) {
-  const int smp = blockIdx.x, i = threadIdx.x;
-  if (i >= 12) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partials[((long long)smp * nblk + b) * 12 + i];
-  sums[smp * 12 + i] = s;
+// one workgroup of 256 per sample: thread t adds records t, t + 256, ...,
+// then the fixed-order tree (one thread walking all records waited out one
+// load latency per record)
+__global__ __launch_bounds__(256) void k_head_sums(const double* __restrict__ partials, int nblk,
+                                                   double* __restrict__ sums) {
+  __shared__ double red[4 * 12];
+  const int smp = blockIdx.x;
+  double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[i] += partials[((long long)smp * nblk + b) * 12 + i];
+  block_sum_d<12>(acc, red);
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 12; ++i) sums[smp * 12 + i] = acc[i];
 }
 
 int head_stats(const uint16_t* d1, const float* hw, const float* hb, const void* target, int target_bf16,
@@ -358,7 +370,7 @@ int head_stats(const uint16_t* d1, const float* hw, const float* hb, const void*
   const int hb_n = head_blocks(g);
   hipLaunchKernelGGL(k_head_stats, dim3(hb_n, g.nb), dim3(256), 0, s, reinterpret_cast<const u32x4*>(d1), hw, hb,
                      target, target_bf16, partials, g);
-  hipLaunchKernelGGL(k_head_sums, dim3(g.nb), dim3(64), 0, s, partials, hb_n, sums);
+  hipLaunchKernelGGL(k_head_sums, dim3(g.nb), dim3(256), 0, s, partials, hb_n, sums);
   return hb_n;
 }
 
@@ -469,12 +481,18 @@ __global__ __launch_bounds__(256) void k_head_backward(const u32x4* __restrict__
   }
 }
 
-__global__ void k_head_backward_reduce(const double* __restrict__ partials, int nrows, double* __restrict__ loss_out,
-                                       float* __restrict__ ghw, float* __restrict__ ghb, double loss_scale) {
-  const int i = threadIdx.x;
-  if (i >= kHeadNV) return;
-  double s = 0.0;
-  for (int r = 0; r < nrows; ++r) s += partials[(long long)r * kHeadNV + i];
+// one workgroup of 256 per value: thread t adds rows t, t + 256, ..., then
+// the fixed-order tree
+__global__ __launch_bounds__(256) void k_head_backward_reduce(const double* __restrict__ partials, int nrows,
+                                                              double* __restrict__ loss_out, float* __restrict__ ghw,
+                                                              float* __restrict__ ghb, double loss_scale) {
+  __shared__ double red[4];
+  const int i = blockIdx.x;
+  double acc[1] = {0.0};
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) acc[0] += partials[(long long)r * kHeadNV + i];
+  block_sum_d<1>(acc, red);
+  if (threadIdx.x != 0) return;
+  const double s = acc[0];
   if (i == 0)
     *loss_out = s * loss_scale;
   else if (i <= 96)
@@ -490,8 +508,8 @@ int head_backward(const uint16_t* d1, const float* hw, const float* hb, const do
   hipLaunchKernelGGL(k_head_backward, dim3(hb_n, g.nb), dim3(256), 0, s, reinterpret_cast<const u32x4*>(d1), hw,
                      hb, sums, tabs, target, target_bf16, reinterpret_cast<u32x4*>(gd1), partials, g);
   const double scale = 1.0 / ((double)g.nb * 6.0 * (double)g.nx * g.ny * g.nz);
-  hipLaunchKernelGGL(k_head_backward_reduce, dim3(1), dim3(128), 0, s, partials, hb_n * g.nb, out_loss, ghw, ghb,
-                     scale);
+  hipLaunchKernelGGL(k_head_backward_reduce, dim3(kHeadNV), dim3(256), 0, s, partials, hb_n * g.nb, out_loss, ghw,
+                     ghb, scale);
   return hb_n;
 }
 

@@ -234,11 +234,16 @@ def test_training_steps_reduce_the_loss():
     # a target correlated with the microstructure
     target = np.repeat(macro[:, :, None, None, None], 1, axis=0) * (1.0 + 0.5 * (phase[:, None] == 1))
     target = target - target.mean(axis=(2, 3, 4), keepdims=True) + macro[:, :, None, None, None]
-    net = fe.UNet(lr=2e-3)
+    # lr 5e-4: the loss falls from the first step.  At 2e-3 it rose elevenfold
+    # within two steps, and whether it then recovered or diverged depended on
+    # the last-bit rounding of the weight-gradient sums (measured with two
+    # summation orders: 0.0136 and 0.958 after 40 steps).
+    net = fe.UNet(lr=5e-4)
     net.set_params(flat32)
     ph = torch.from_numpy(phase).cuda()
     tg = dev_f32(target)
     losses = [net.train_step(ph, E, nu, macro, tg) for _ in range(40)]
+    assert losses[1] < losses[0], losses
     assert losses[-1] < 0.5 * losses[0], losses
     net.close()
 
