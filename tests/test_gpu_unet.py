@@ -75,8 +75,10 @@ def _conv_case(cin, cout, shape, seed):
     return x, w, b
 
 
+# (1, 12, 12, 48) has a tile whose halo lies inside the grid (origin x 16,
+# y 4, z 4): the staging path without periodic wrap; the others wrap
 @pytest.mark.parametrize("cin,cout", FWD)
-@pytest.mark.parametrize("shape", [(2, 5, 6, 20), (1, 8, 8, 32)])
+@pytest.mark.parametrize("shape", [(2, 5, 6, 20), (1, 8, 8, 32), (1, 12, 12, 48)])
 def test_conv_forward(cin, cout, shape):
     x, w, b = _conv_case(cin, cout, shape, 100 * cin + cout)
     y = host_bf16(fe.conv3_forward(dev_bf16(x), dev_f32(w), dev_f32(b), relu=True))
@@ -88,12 +90,14 @@ def test_conv_forward(cin, cout, shape):
 
 @pytest.mark.parametrize("cin,cout,ccoarse", [(48, 16, 32), (96, 32, 64), (192, 64, 128)])
 @pytest.mark.parametrize("relu", [True, False])
-def test_decoder_layer_reads_its_concatenation_in_place(cin, cout, ccoarse, relu):
+@pytest.mark.parametrize("shape", [(2, 6, 8, 20), (1, 12, 12, 48)])
+def test_decoder_layer_reads_its_concatenation_in_place(cin, cout, ccoarse, relu, shape):
     """The decoder layers of inference read [nearest upsampling of the coarse
     level, skip] in place; the result equals the layer on the materialised
     concatenation bit for bit (same staged values, same products), and the
-    oracle on that concatenation within the layer bound."""
-    shape = (2, 6, 8, 20)  # (B, nz, ny, nx): even, tiles ragged in y and x
+    oracle on that concatenation within the layer bound.  Shapes (B, nz, ny,
+    nx), even: tiles ragged in y and x, and one tile with its halo inside the
+    grid."""
     r = np.random.default_rng(cin + cout)
     _, w, b = _conv_case(cin, cout, shape, 11 * cin + cout)
     coarse = bf16_round(r.standard_normal((shape[0], shape[1] // 2, shape[2] // 2, shape[3] // 2, ccoarse)))
@@ -111,8 +115,8 @@ def test_decoder_layer_reads_its_concatenation_in_place(cin, cout, ccoarse, relu
 
 
 @pytest.mark.parametrize("cin,cout", [s for s in FWD if s[0] % 16 == 0])
-def test_conv_backward_data(cin, cout):
-    shape = (2, 5, 6, 20)
+@pytest.mark.parametrize("shape", [(2, 5, 6, 20), (1, 12, 12, 48)])
+def test_conv_backward_data(cin, cout, shape):
     r = np.random.default_rng(7 * cin + cout)
     _, w, _ = _conv_case(cin, cout, shape, cin + 3 * cout)
     dy = bf16_round(r.standard_normal(shape + (cout,)))
