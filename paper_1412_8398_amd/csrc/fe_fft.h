@@ -99,11 +99,13 @@ constexpr bool plan_ok(int N, int E) { return N % E == 0 && plan_ns(N, E, plan_s
 //  strided passes: up to 32 (2^a) or 24 (3*2^a); lengths up to 128 take 16
 //  or 12, so that a 256-thread tile needs at most 32 KiB of LDS (four
 //  workgroups per CU in the persistent batched kernel)
-//  x passes: up to 16 (2^a) or 12 (3*2^a) with 3 components, 8 / 12 with 6
+//  x passes: 8 (2^a) or 12 (3*2^a) with 3 components (float64: 4 or 6),
+//  8 / 12 with 6
 constexpr int e_strided(int N) {
   return N % 3 == 0 ? (N >= 192 ? 24 : (N >= 12 ? 12 : N)) : (N >= 256 ? 32 : (N >= 16 ? 16 : N));
 }
 constexpr int e_x3(int N) { return N % 3 == 0 ? (N >= 12 ? 12 : N) : (N >= 8 ? 8 : N); }
+constexpr int e_x3_wide(int N) { return N % 3 == 0 ? (N >= 6 ? 6 : N) : (N >= 4 ? 4 : N); }
 constexpr int e_x6(int N) { return N % 3 == 0 ? (N >= 12 ? 12 : N) : (N >= 8 ? 8 : N); }
 
 // One Stockham stage over NC components held in registers.  `Lds` maps

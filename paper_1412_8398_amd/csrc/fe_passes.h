@@ -42,7 +42,10 @@ struct StridedCfg {
 // x passes: LPB lines per workgroup, P = N/E threads per line.
 template <typename T, int N, int NC>
 struct LineCfg {
-  static constexpr int E = NC == 3 ? e_x3(N) : e_x6(N);
+  // float64 lines of three components hold half the elements per thread: a
+  // workgroup of 4 lines at 8 elements would take 96 KiB of LDS at 512 (one
+  // workgroup, one wave per SIMD)
+  static constexpr int E = NC == 3 ? (sizeof(T) == 8 ? e_x3_wide(N) : e_x3(N)) : e_x6(N);
   static constexpr int P = N / E;
   static constexpr int LPB = imax(1, 256 / P);
   static constexpr int NT = LPB * P;
