@@ -5,7 +5,7 @@ definition), the solve from it reaches the same equilibrium, and it saves
 iterations, no more than the contraction model allows: a start whose error
 is e times that of eps_bar saves at most about log(e) / log(rho) iterations
 (rho: the plain run's contraction per iteration).  Measured on 16 cells at
-512^3: 0.94 iterations saved per cell against a prediction that costs 5.8."""
+512^3: 0.94 iterations saved per cell against a prediction that costs 5.4."""
 import os
 
 import numpy as np
@@ -15,7 +15,7 @@ from microstructure import batch_samples
 
 torch = pytest.importorskip("torch")
 import paper_1412_8398_amd as fe  # noqa: E402
-from paper_1412_8398_amd.warmstart import DEFAULT_WEIGHTS, compare_one, load_net  # noqa: E402
+from paper_1412_8398_amd.warmstart import DEFAULT_WEIGHTS, compare_one, load_net, scaled_starts  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -68,3 +68,25 @@ def test_a_start_that_cannot_converge_falls_back_to_the_applied_strain():
     assert fell_back
     assert r.status == fe.FE_OK == plain.status and r.iterations == plain.iterations
     assert np.array_equal(np.asarray(r.mean_stress), np.asarray(plain.mean_stress))
+
+
+def test_starts_between_the_applied_strain_and_the_solution():
+    """The starts that bound what a better prediction could save: the
+    network's error scaled by 0 is the converged strain itself, from which the
+    solve stops at once (at most one iteration: its float32 eta^0 may sit at
+    the tolerance the float64 check met); from eps_bar plus 90% of the exact
+    fluctuation it needs fewer iterations than from eps_bar, and from eps_bar
+    plus half of it no fewer than from 90%."""
+    s = batch_samples(1, 4242, sizes=(48,))[0]
+    ph = torch.from_numpy(s.phase).cuda()
+    E, nu = [1.0, 50.0], [s.nu, s.nu]
+    with fe.Plan(48, green="R", scheme="AS", precision="fp32", max_iter=3000) as plan:
+        eps = torch.empty((6, 48, 48, 48), dtype=torch.float32, device="cuda")
+        plain = plan.solve(ph, E, nu, s.macro_strain, 1e-6, strain=eps, raise_on_error=False)
+        assert plain.status == fe.FE_OK
+        pred = eps + 0.01 * torch.randn_like(eps)  # a stand-in prediction near the solution
+        its = scaled_starts(plan, ph, E, nu, s.macro_strain, 1e-6, eps, pred, scales=(0.0,), shares=(0.5, 0.1))
+    print(plain.iterations, its, flush=True)
+    assert its["pred_x0"] <= 1
+    assert its["fluct_e0.1"] < plain.iterations
+    assert its["fluct_e0.1"] <= its["fluct_e0.5"] <= plain.iterations
