@@ -1,10 +1,10 @@
 """HBM traffic per launch of each pass from two rocprofv3 counter runs.
 
-    rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pf -o pf -- \\
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d prof/pf -o pf -- \\
         python3 bench.py --size L --steps 3 --warmup 1 --no-cpu-baseline --no-tti --no-fp64 --copy-calibration
-    rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pw -o pw -- (same)
-    python -m paper_1412_8398_amd.traffic --size L --fetch gpurun_out/pf/pf_counter_collection.csv \\
-        --write gpurun_out/pw/pw_counter_collection.csv --out profiles/traffic_ASR_fp32_L.json
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d prof/pw -o pw -- (same)
+    python -m paper_1412_8398_amd.traffic --size L --fetch prof/pf/pf_counter_collection.csv \\
+        --write prof/pw/pw_counter_collection.csv --out profiles/traffic_ASR_fp32_L.json
 
 The counters are read in KiB per dispatch.  The 1 GiB device copy that
 ``bench.py --copy-calibration`` runs first (a plain read-and-write kernel of
