@@ -11,7 +11,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
-from bench import pass_bytes  # noqa: E402
+from bench import pass_bytes, spectrum_bytes  # noqa: E402
 from paper_1412_8398_amd import traffic  # noqa: E402
 
 
@@ -28,6 +28,13 @@ def test_pass_bytes_per_voxel():
         assert 24 * N <= b[k] <= 24 * N * (1 + 4 / L)
     it = sum(v for k, v in b.items() if k != "pointwise") / N
     assert 193 <= it <= 194
+
+
+def test_spectrum_bytes_follow_the_z_blocking():
+    # half spectra: nz/2 + 1 planes rounded up to blocks of 8 (4, 2, 1 where 8 does not divide nz)
+    assert spectrum_bytes(512) == 3 * 264 * 512 * 512 * 8
+    assert spectrum_bytes(1024) == 3 * 520 * 1024 * 1024 * 8
+    assert spectrum_bytes(36) == 3 * 20 * 36 * 36 * 8  # 36: blocks of 4, 19 planes -> 20
 
 
 def _write(path, counter, rows):
