@@ -91,8 +91,8 @@ __global__ __launch_bounds__(DX * DY) void k_update_div(const T* __restrict__ U,
 }
 
 int div_partial_count(Dims d) {
-  // the smallest tiles give the most workgroups (float grids up to 128 wide
-  // and double grids both use 32 x 8)
+  // the smallest tiles give the most workgroups (grids up to 128 wide and the
+  // float64 verification use 32 x 8; wider grids 128 x 8, or 64 x 8 in float64)
   return div_grid<Tile<float>::DX, Tile<float>::DY>(d).blocks > div_grid<32, 8>(d).blocks
              ? div_grid<Tile<float>::DX, Tile<float>::DY>(d).blocks
              : div_grid<32, 8>(d).blocks;
@@ -490,7 +490,7 @@ int launch_verify_div(const TS* eps, const uint8_t* phase, const PhaseCoef<doubl
 template <typename TS>
 int launch_div64(const TS* eps, const uint8_t* phase, const PhaseCoef<double>* coef, double* Dtau, TS* Dsig,
                  double* partials, Dims d, int op, hipStream_t s, Batch bt, int nsamp) {
-  constexpr int DX = Tile<double>::DX, DY = Tile<double>::DY;
+  constexpr int DX = VerifyTile::DX, DY = VerifyTile::DY;
   const DivGrid gd = div_grid<DX, DY>(d);
   const dim3 grid(gd.blocks, nsamp);
   if (op == OP_ROT)

@@ -108,8 +108,9 @@ __device__ __forceinline__ void grad_rot(const T (&u)[8][3], T (&gr)[3][3]) {
 // Corner tile (x by y) of a workgroup, by the type held in LDS.  The -x halo
 // voxel of a tile costs a whole 128-byte line per row (and U a second one at
 // +x): wide tiles make that a small fraction.  Float: 128 x 8 (1024 threads,
-// 94 KiB of LDS); double: 32 x 8 (a double 128 x 8 tile does not fit in
-// 160 KiB, and 64 x 8 ran the float64 verification stencil slower).
+// 94 KiB of LDS); double: 64 x 8 (512 threads, 104 KiB; a double 128 x 8
+// tile does not fit in 160 KiB).  The float64 verification of a strain keeps
+// 32 x 8 (VerifyTile): 64 x 8 ran it slower.
 template <typename T>
 struct Tile;
 template <>
@@ -118,6 +119,9 @@ struct Tile<float> {
 };
 template <>
 struct Tile<double> {
+  static constexpr int DX = 64, DY = 8;
+};
+struct VerifyTile {
   static constexpr int DX = 32, DY = 8;
 };
 
@@ -543,15 +547,15 @@ __device__ __forceinline__ void reduce_body(const double* __restrict__ partials,
 }
 
 // Corner tile of the divergence walk for a grid: Tile<T>, or 32 x 8 (256
-// threads) for float grids at most 128 wide (the tile of the persistent
-// batched kernel; a 128-wide tile would leave most of a small grid's row idle).
+// threads) for grids at most 128 wide (the tile of the persistent batched
+// kernel; a wider tile would leave most of a small grid's row idle).
 template <typename T>
 struct SmallTile {
   static constexpr int DX = 32, DY = 8;
 };
 template <typename T, class F>
 inline void with_tile(const Dims& d, F&& f) {
-  if (sizeof(T) == 4 && d.nx <= 128)
+  if (d.nx <= 128)
     f(std::integral_constant<int, SmallTile<T>::DX>(), std::integral_constant<int, SmallTile<T>::DY>());
   else
     f(std::integral_constant<int, Tile<T>::DX>(), std::integral_constant<int, Tile<T>::DY>());
